@@ -1,0 +1,236 @@
+/*
+ * se1p.h -- C ABI of the MI355X (gfx950) Spectral Ewald library for singly
+ * periodic Coulomb systems (SE1P; Saffar Shamshirgar & Tornberg,
+ * "The Spectral Ewald method for singly periodic domains").
+ *
+ * Problem (section 1, eq. coulomb with the lattice P_1 of section 2.1):
+ * N point charges q_n at x_n in a box [0,L1) x [0,L2) x [0,L3), periodic along
+ * z (index 2) with period L3 and free along x and y, with sum_n q_n = 0.  For
+ * every particle the library returns the potential
+ *
+ *     phi_m = phi^R_m + phi^F_m + phi^self_m           (eq. full_potential)
+ *
+ * and the field E_m = -grad_{x_m} phi_m, so that the force is F_m = q_m E_m
+ * and the energy U = 1/2 sum_m q_m phi_m (section 3.5 read with the usual 1/2;
+ * the paper's printed energy omits it while its force formula keeps it).
+ *
+ *   phi^F   Fourier-space part by the SE1P method (Algorithm 1): Gaussian
+ *           gridding, the adaptive FFT of Algorithm 2 (k3 = 0 slab on an
+ *           s0-upsampled grid with the truncated Green's function of
+ *           eq. G_kappa_k, slabs 0 < |k3| <= 2 pi n_l / L3 upsampled by s_l,
+ *           the rest not upsampled), scaling (eq. scale_1p), the inverse of
+ *           Algorithm 3, and gathering (eq. se1p_complete_discretized) with
+ *           its analytic gradient for E (eq. force_se1p).
+ *   phi^R   real-space erfc sum over z-images within the cut-off rc
+ *           (eq. ewald1p_real; field eq. force_real).
+ *   phi^self  -2 xi q_m / sqrt(pi) (eq. ewald1p_self).
+ *
+ * Conventions for every entry point:
+ *   - Return value: 0 on success, a negative SE1P_ERR_* code otherwise;
+ *     se1p_error_string() turns it into text.  Argument checks run on the host
+ *     before anything is enqueued; nothing is enqueued when a check fails.
+ *   - Device pointers are HIP device memory on the plan's device.  The caller
+ *     owns every particle and output buffer; the plan owns its workspace.
+ *     No entry point allocates memory except se1p_plan_create (and
+ *     se1p_batch_create); se1p_plan_destroy frees it.
+ *   - Work is enqueued on the plan's stream (hipStream_t passed as void*,
+ *     NULL = the default stream) without synchronising, except where a
+ *     function says otherwise.
+ *   - Floating-point buffers are double for SE1P_FP64 plans and float for
+ *     SE1P_FP32 plans; the energy is always double.
+ *   - Positions are row-major N x 3 (x, y, z).  x and y must lie in [0, L1)
+ *     and [0, L2); z may be any finite value and is wrapped into [0, L3).
+ */
+#ifndef SE1P_H
+#define SE1P_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define SE1P_OK               0
+#define SE1P_ERR_ARG         -1  /* NULL pointer, bad size, unknown flag */
+#define SE1P_ERR_PARAM       -2  /* inconsistent method parameters */
+#define SE1P_ERR_NONNEUTRAL  -3  /* |sum q| > 1e-10 sum |q| (section 2.1 needs neutrality) */
+#define SE1P_ERR_OUT_OF_BOX  -4  /* x or y outside [0,L1) x [0,L2), or non-finite */
+#define SE1P_ERR_HIP         -5  /* a HIP runtime call failed */
+#define SE1P_ERR_NOMEM       -6  /* device allocation failed */
+#define SE1P_ERR_TOO_MANY    -7  /* N larger than the plan's n_max */
+#define SE1P_ERR_UNSUPPORTED -8  /* valid request outside what this build supports */
+
+/* ---- precision ---------------------------------------------------------- */
+#define SE1P_FP64 0
+#define SE1P_FP32 1
+
+/* ---- components for se1p_eval (bit mask) -------------------------------- */
+#define SE1P_KSPACE        1u  /* phi^F, E^F (Algorithm 1) */
+#define SE1P_REAL          2u  /* phi^R, E^R (eq. ewald1p_real, eq. force_real) */
+#define SE1P_SELF          4u  /* phi^self (eq. ewald1p_self) */
+#define SE1P_ALL           7u
+#define SE1P_CHECK_INPUT  16u  /* validate positions and neutrality on the device;
+                                  synchronises the plan's stream */
+#define SE1P_NO_NEUTRAL   32u  /* evaluate the SE1P operator for any charge
+                                  vector (used for adjoint products); the
+                                  result is the discrete operator applied to
+                                  q, not a physical Ewald sum */
+
+/*
+ * Method parameters (Algorithm 1 input, section 4.3 recipe).
+ *   box      L1, L2, L3; z (index 2) is periodic.
+ *   xi       Ewald splitting parameter (> 0).
+ *   M3       grid points along z (even, >= P); h = L3 / M3.  The free
+ *            directions use the same h over ceil(L_d / h) cells, extended by
+ *            P points for the Gaussian support (L~ = L + P h, section 3.1).
+ *   P        points in the support of the truncated Gaussians per direction
+ *            (even, 4..32).  eta = P xi^2 h^2 / (c^2 pi), c = 0.95
+ *            (eq. comp_eta).
+ *   n_l      local pad size: modes 0 < |n3| <= n_l are upsampled by s_l
+ *            (eq. I, eq. upsamplings).
+ *   s_l      upsampling factor of the local pad set (>= 1).
+ *   s0       upsampling factor of the k3 = 0 slab.  The padded period must
+ *            be at least the support extent plus R = |(L~1, L~2)|
+ *            (section 3.2, R = sqrt(2) L~ for a square cross-section), i.e.
+ *            s0 >= 1 + sqrt(2) for a square cross-section; smaller values are
+ *            raised to that minimum.
+ *   rc       real-space cut-off (> 0 when SE1P_REAL is requested).
+ *   pad_free extra grid points appended in each free direction beyond
+ *            M + P (>= 0).  The paper's extension is pad_free = 0; a few
+ *            extra zero points push the periodic images of the slabs that
+ *            are not upsampled further away at almost no cost.
+ *   precision SE1P_FP64 or SE1P_FP32.
+ * Padded FFT lengths are rounded up to products of 2, 3 and 5.
+ */
+typedef struct se1p_params {
+    double box[3];
+    double xi;
+    int    M3;
+    int    P;
+    int    n_l;
+    double s_l;
+    double s0;
+    double rc;
+    int    pad_free;
+    int    precision;
+} se1p_params;
+
+/* Derived quantities of a plan (read-only). */
+typedef struct se1p_plan_info {
+    double h;            /* grid spacing L3 / M3 */
+    double eta;          /* Gaussian width parameter, eq. comp_eta */
+    double R;            /* truncation radius of the k3 = 0 Green's function */
+    int    M[2];         /* cells across the charge box in x, y */
+    int    Mt[2];        /* extended grid in x, y (>= M + P, FFT-friendly) */
+    int    M3;
+    int    P;
+    int    n0[2];        /* padded 2D FFT size of the k3 = 0 slab */
+    int    nl[2];        /* padded 2D FFT size of the slabs 0 < |n3| <= n_l */
+    int    n_l;
+    int    nslab;        /* slabs transformed: n3 = 0 .. M3/2 (Hermitian half) */
+    int    precision;
+    long long n_max;
+    size_t workspace_bytes;
+} se1p_plan_info;
+
+typedef struct se1p_plan se1p_plan;
+
+/*
+ * se1p_suggest_params -- host only.  Parameter selection of section 4.3:
+ * given a target RMS error tol, the box, N and Q = sum q^2, pick
+ *   - M3 = 2 k_inf from the Fourier truncation estimate (eq. kinf) when
+ *     M3_in <= 0, else use M3_in and pick the largest xi that meets the same
+ *     estimate (xi_in <= 0), or the given xi_in;
+ *   - rc from the real-space estimate (eq. rc);
+ *   - P from eq. approximation_error_oneterm when P_in <= 0 (rounded up to
+ *     even), else P_in;
+ *   - s_l from eq. choose_sl generalised to a non-square box
+ *     (exp(-2 pi s_l L~ / L3) < tol) and n_l from eq. choose_nl (M3 ~ 10 n_l)
+ *     when n_l_in < 0, else n_l_in;
+ *   - s0 = 1 + sqrt(2) (minimum of section 3.4).
+ * precision: SE1P_FP64 or SE1P_FP32.  Writes *out; returns an error code.
+ */
+int se1p_suggest_params(double tol, const double box[3], long long N,
+                        double Q, double xi_in, int M3_in, int P_in,
+                        int n_l_in, int precision, se1p_params* out);
+
+/*
+ * se1p_plan_create -- validates *params, derives the grid geometry, builds
+ * the k3 = 0 scaling table (eq. G_kappa_k, FP64 on the host), the FFT
+ * tables, and allocates the device workspace for up to n_max particles on
+ * the current HIP device.  stream: hipStream_t (NULL = default stream).
+ * On success *out owns everything; free it with se1p_plan_destroy.
+ */
+int se1p_plan_create(const se1p_params* params, long long n_max,
+                     void* stream, se1p_plan** out);
+
+/* Releases the plan and its device workspace (synchronises its stream). */
+int se1p_plan_destroy(se1p_plan* plan);
+
+/* Copies the derived geometry of the plan into *info. */
+int se1p_plan_get_info(const se1p_plan* plan, se1p_plan_info* info);
+
+/* Changes the stream later calls enqueue on. */
+int se1p_set_stream(se1p_plan* plan, void* stream);
+
+/*
+ * se1p_eval -- one evaluation.
+ *   N          number of particles (1 .. n_max).
+ *   x          device, N x 3 positions (row-major), FP64/FP32 per plan.
+ *   q          device, N charges.  Must sum to zero (within 1e-10 sum |q|)
+ *              unless SE1P_NO_NEUTRAL; only checked with SE1P_CHECK_INPUT.
+ *   phi        device, N potentials out, or NULL.
+ *   efield     device, N x 3 fields out (E = -grad phi), or NULL.
+ *   energy     device, one double out: U = 1/2 sum q phi over the requested
+ *              components, or NULL.
+ *   flags      SE1P_KSPACE | SE1P_REAL | SE1P_SELF, optionally with
+ *              SE1P_CHECK_INPUT and SE1P_NO_NEUTRAL.
+ * Components left out contribute zero.  Without SE1P_CHECK_INPUT,
+ * out-of-box x/y are clamped to the box edge cells (memory-safe, result
+ * unspecified).
+ */
+int se1p_eval(se1p_plan* plan, long long N, const void* x, const void* q,
+              void* phi, void* efield, double* energy, unsigned flags);
+
+/*
+ * Stages of the k-space path, for testing and for callers that bring their
+ * own real-space part.  All enqueue on the plan's stream.
+ *
+ * se1p_spread -- step 2 of Algorithm 1 (eq. spread_1p): H on the grid.
+ *   grid: device, M3 x Mt1 x Mt2 values (z slowest, y fastest); grid point
+ *   (l, i, j) sits at (x, y, z) = ((i - P/2) h, (j - P/2) h, l h).
+ *   Values include the Gaussian normalisation (2 xi^2 / (pi eta))^{3/2}.
+ */
+int se1p_spread(se1p_plan* plan, long long N, const void* x, const void* q,
+                void* grid);
+
+/*
+ * se1p_kspace_solve -- steps 3-5 of Algorithm 1 on a grid from se1p_spread:
+ * AFT (Algorithm 2), scaling (eq. scale_1p, with the (kappa, k3) = (0, 0)
+ * coefficient set to zero), AIFT (Algorithm 3).  grid_in and grid_out have
+ * the layout above (they may alias).  The output is normalised so that
+ * phi^F_m = 4 pi h^3 sum_grid Htilde g(x_m - x_grid), with g the normalised
+ * truncated Gaussian of eq. spread_1p.
+ */
+int se1p_kspace_solve(se1p_plan* plan, const void* grid_in, void* grid_out);
+
+/*
+ * se1p_gather -- step 6 of Algorithm 1 and its analytic gradient: phi^F and
+ * E^F at the particles from a grid produced by se1p_kspace_solve.
+ * phi, efield as in se1p_eval (either may be NULL).
+ */
+int se1p_gather(se1p_plan* plan, long long N, const void* x,
+                const void* grid, void* phi, void* efield);
+
+/* Human-readable text for an error code (static storage). */
+const char* se1p_error_string(int code);
+
+/* Library version string (static storage). */
+const char* se1p_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SE1P_H */

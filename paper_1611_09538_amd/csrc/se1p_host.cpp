@@ -1,0 +1,709 @@
+// se1p_host.cpp -- host side of the SE1P library: parameter selection,
+// planning (grid geometry, padded FFT sizes, FP64 k3 = 0 scaling table, FFT
+// tables), workspace, argument checks and the C ABI of include/se1p.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/se1p.h"
+#include "se1p_internal.h"
+
+namespace se1p {
+size_t scan_temp_bytes(long long n);
+}
+
+using namespace se1p;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kShapeC = 0.95;  // c in eq. comp_eta
+
+// smallest integer >= n whose only prime factors are 2, 3, 5
+int nice_size(int n) {
+    if (n < 1) n = 1;
+    for (int m = n;; ++m) {
+        int r = m;
+        while (r % 2 == 0) r /= 2;
+        while (r % 3 == 0) r /= 3;
+        while (r % 5 == 0) r /= 5;
+        if (r == 1) return m;
+    }
+}
+
+bool factorize(int n, FftDesc& d) {
+    d.n = n;
+    d.nrad = 0;
+    int r = n;
+    auto push = [&](int f) {
+        if (d.nrad >= kMaxRad) return false;
+        d.rad[d.nrad++] = f;
+        return true;
+    };
+    while (r % 4 == 0) { if (!push(4)) return false; r /= 4; }
+    while (r % 2 == 0) { if (!push(2)) return false; r /= 2; }
+    while (r % 3 == 0) { if (!push(3)) return false; r /= 3; }
+    while (r % 5 == 0) { if (!push(5)) return false; r /= 5; }
+    return r == 1;
+}
+
+// Fourier transform of the truncated 2D Green's function
+// (eqs. g_zeromod, g_zeromod0), FP64.
+double G_R(double kappa, double R) {
+    const double x = R * kappa;
+    if (kappa == 0.0) return R * R / 4.0 * (1.0 - 2.0 * std::log(R));
+    if (x < 1e-3) {
+        // series: (1 - J0(x))/k^2 = R^2/4 (1 - x^2/16 + x^4/576),
+        //         J1(x)/k        = R/2 (1 - x^2/8 + x^4/192)
+        const double x2 = x * x;
+        const double a = R * R / 4.0 * (1.0 - x2 / 16.0 + x2 * x2 / 576.0);
+        const double b = R * std::log(R) * R / 2.0 * (1.0 - x2 / 8.0 + x2 * x2 / 192.0);
+        return a - b;
+    }
+    return (1.0 - ::j0(x)) / (kappa * kappa) - R * std::log(R) * ::j1(x) / kappa;
+}
+
+double lambert_w(double x) {  // principal branch, x >= 0
+    if (x <= 0.0) return 0.0;
+    double w = x < 1.0 ? x : std::log(x) - std::log(std::log(x) + 1.0);
+    if (w < 0.0) w = 0.0;
+    for (int i = 0; i < 100; ++i) {
+        const double ew = std::exp(w);
+        const double f = w * ew - x;
+        const double wn = w - f / (ew * (w + 1.0) - (w + 2.0) * f / (2.0 * w + 2.0));
+        if (std::fabs(wn - w) < 1e-15 * (1.0 + std::fabs(wn))) return wn;
+        w = wn;
+    }
+    return w;
+}
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct se1p_plan {
+    se1p_params prm;
+    int prec = 0;           // SE1P_FP64 / SE1P_FP32
+    size_t es = 8;          // element size
+    long long n_max = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    Geo g{};
+    BinGeo bg{};
+    double cg = 0.0;        // (2 xi^2 / (pi eta))^{3/2}
+    double R = 0.0;
+    int M1 = 0, M2 = 0;
+    int n0[2] = {0, 0}, nl[2] = {0, 0};
+    int nslab = 0;
+    int CZ = 0, KP = 0;
+    std::vector<SlabDesc> slabs;
+    FftDesc dz{};
+    long long tw_elems = 0;
+    long long slab_elems = 0;
+
+    // device memory (single allocation, carved)
+    void* base = nullptr;
+    size_t ws_bytes = 0;
+    int *key_lex = nullptr, *key_blk = nullptr, *slot_lex = nullptr, *slot_blk = nullptr;
+    int *cnt_lex = nullptr, *cnt_blk = nullptr;
+    int *lex_i[5] = {}, *blk_i[5] = {};   // cx, cy, cz, perm, start
+    void *lex_f[4] = {}, *blk_f[4] = {};  // x, y, z, q
+    void* scan_tmp = nullptr;
+    size_t scan_bytes = 0;
+    void *wz = nullptr, *wxp = nullptr, *wyq = nullptr;
+    void* Hpart = nullptr;
+    long long pstride = 0;
+    void* Fz = nullptr;
+    void* G = nullptr;
+    void* Ht = nullptr;
+    void* S0 = nullptr;
+    void* tw = nullptr;
+    SlabDesc* d_slabs = nullptr;
+    void *phiF = nullptr, *EF = nullptr, *phiR = nullptr, *ER = nullptr;
+    double* partials = nullptr;
+    int nblk_comb = 0;
+    int* flag = nullptr;
+    double* qsum = nullptr;
+};
+
+namespace {
+
+int check_params(const se1p_params& p) {
+    for (int d = 0; d < 3; ++d)
+        if (!(p.box[d] > 0.0) || !std::isfinite(p.box[d])) return SE1P_ERR_PARAM;
+    if (!(p.xi > 0.0) || !std::isfinite(p.xi)) return SE1P_ERR_PARAM;
+    if (p.M3 < 4 || (p.M3 & 1)) return SE1P_ERR_PARAM;
+    if (p.P < 4 || p.P > kMaxP || (p.P & 1) || p.P > p.M3) return SE1P_ERR_PARAM;
+    if (p.n_l < 0) return SE1P_ERR_PARAM;
+    if (!(p.s_l >= 1.0) || !(p.s_l <= 16.0)) return SE1P_ERR_PARAM;
+    if (!(p.s0 >= 0.0) || !(p.s0 <= 16.0)) return SE1P_ERR_PARAM;
+    if (!(p.rc >= 0.0) || !std::isfinite(p.rc)) return SE1P_ERR_PARAM;
+    if (p.precision != SE1P_FP64 && p.precision != SE1P_FP32) return SE1P_ERR_PARAM;
+    if (p.pad_free < 0 || p.pad_free > 1024) return SE1P_ERR_PARAM;
+    const double h = p.box[2] / p.M3;
+    for (int d = 0; d < 2; ++d) {
+        const double m = std::ceil(p.box[d] / h - 1e-9);
+        if (m > 4096) return SE1P_ERR_PARAM;
+    }
+    return SE1P_OK;
+}
+
+// Gather block shape: lanes are particles, so aim for blocks holding close
+// to one wave of particles while keeping the union of the supports small.
+void choose_blocks(se1p_plan& pl) {
+    const double ncells = (double)pl.M1 * pl.M2 * pl.g.M3;
+    const double rho = (double)std::max<long long>(pl.n_max, 1) / ncells;
+    const int P = pl.g.P;
+    double best = 1e300;
+    int bx = 1, by = 2, bz = 1;
+    const int bys[3] = {2, 4, 8};
+    const int bzs[4] = {1, 2, 4, 8};
+    for (int iy = 0; iy < 3; ++iy)
+        for (int iz = 0; iz < 4; ++iz) {
+            const int BY = bys[iy], BZ = bzs[iz];
+            if (pl.g.M3 % BZ) continue;
+            for (int BX = 1; BX <= 16; ++BX) {
+                const double m = rho * BX * BY * BZ;   // expected particles
+                const double waves = std::max(1.0, std::ceil(m / 64.0 + 0.5));
+                const double per_wave_rows =
+                    (double)(BX + P - 1) * (BY + P - 1) * (BZ + P - 1);
+                // cost per particle ~ union points swept per lane / particles
+                const double cost = waves * per_wave_rows / std::max(m, 1e-3);
+                if (cost < best) { best = cost; bx = BX; by = BY; bz = BZ; }
+            }
+        }
+    BinGeo& b = pl.bg;
+    b.BX = bx; b.BY = by; b.BZ = bz;
+    b.nbx = (pl.M1 + bx - 1) / bx;
+    b.nby = (pl.M2 + by - 1) / by;
+    b.nbz = pl.g.M3 / bz;
+    b.cpb = bx * by * bz;
+    b.ncell_lex = (long long)pl.g.M3 * pl.M1 * pl.M2;
+    b.ncell_blk = (long long)b.nbx * b.nby * b.nbz * b.cpb;
+}
+
+// Spread chunking: CZ z-cells per wave, KP partial grids with KP | M3/CZ and
+// KP*CZ >= CZ + P - 1.  Prefer enough waves to fill the chip, then fewer
+// partial grids.
+void choose_spread(se1p_plan& pl) {
+    const int M3 = pl.g.M3, P = pl.g.P;
+    const long long tiles = (long long)((pl.g.Mt1 + 7) / 8) * ((pl.g.Mt2 + 7) / 8);
+    int bestCZ = 1, bestKP = M3;
+    double bestScore = -1e300;
+    const int czs[4] = {8, 4, 2, 1};
+    for (int i = 0; i < 4; ++i) {
+        const int CZ = czs[i];
+        if (M3 % CZ) continue;
+        const int ncz = M3 / CZ;
+        const int need = (CZ + P - 1 + CZ - 1) / CZ;
+        int KP = -1;
+        for (int k = need; k <= ncz; ++k)
+            if (ncz % k == 0) { KP = k; break; }
+        if (KP < 0) continue;
+        const double waves = (double)tiles * ncz;
+        const double fill = std::min(1.0, waves / 2048.0);
+        const double score = fill * 4.0 - 0.05 * KP;
+        if (score > bestScore) { bestScore = score; bestCZ = CZ; bestKP = KP; }
+    }
+    pl.CZ = bestCZ;
+    pl.KP = bestKP;
+}
+
+template <typename T>
+DevParticles<T> particles(const se1p_plan& pl, bool lex) {
+    DevParticles<T> d;
+    void* const* f = lex ? pl.lex_f : pl.blk_f;
+    int* const* i = lex ? pl.lex_i : pl.blk_i;
+    d.x = (T*)f[0]; d.y = (T*)f[1]; d.z = (T*)f[2]; d.q = (T*)f[3];
+    d.cx = i[0]; d.cy = i[1]; d.cz = i[2]; d.perm = i[3]; d.start = i[4];
+    return d;
+}
+
+int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
+    pl.prm = p;
+    pl.prec = p.precision;
+    pl.es = (p.precision == SE1P_FP64) ? 8 : 4;
+    pl.n_max = n_max;
+    Geo& g = pl.g;
+    g.M3 = p.M3;
+    g.P = p.P;
+    g.L3 = p.box[2];
+    g.h = p.box[2] / p.M3;
+    g.inv_h = 1.0 / g.h;
+    g.xi = p.xi;
+    g.eta = p.P * p.xi * p.xi * g.h * g.h / (kShapeC * kShapeC * kPi);
+    g.alpha = 2.0 * p.xi * p.xi / g.eta;
+    pl.cg = std::pow(2.0 * p.xi * p.xi / (kPi * g.eta), 1.5);
+    pl.M1 = (int)std::ceil(p.box[0] / g.h - 1e-9);
+    pl.M2 = (int)std::ceil(p.box[1] / g.h - 1e-9);
+    if (pl.M1 < 1) pl.M1 = 1;
+    if (pl.M2 < 1) pl.M2 = 1;
+    g.M1 = pl.M1;
+    g.M2 = pl.M2;
+    choose_blocks(pl);
+    // Extended grid: M + P plus room for whole gather blocks, FFT-friendly.
+    g.Mt1 = nice_size(std::max(pl.bg.nbx * pl.bg.BX + p.P, pl.M1 + p.P + p.pad_free));
+    g.Mt2 = nice_size(std::max(pl.bg.nby * pl.bg.BY + p.P, pl.M2 + p.P + p.pad_free));
+    g.ncol = (long long)g.Mt1 * g.Mt2;
+    choose_spread(pl);
+
+    // k3 = 0 slab: R spans the support region; the padded period must hold
+    // the support plus R (section 3.2; s0 >= 1 + sqrt 2 for a square).
+    const double e1 = (pl.M1 + p.P) * g.h, e2 = (pl.M2 + p.P) * g.h;
+    pl.R = std::hypot(e1, e2);
+    const int rcell = (int)std::ceil(pl.R / g.h - 1e-9);
+    pl.n0[0] = nice_size(std::max({(int)std::ceil(p.s0 * (pl.M1 + p.P) - 1e-9),
+                                   pl.M1 + p.P + rcell, g.Mt1}));
+    pl.n0[1] = nice_size(std::max({(int)std::ceil(p.s0 * (pl.M2 + p.P) - 1e-9),
+                                   pl.M2 + p.P + rcell, g.Mt2}));
+    pl.nl[0] = nice_size(std::max((int)std::ceil(p.s_l * (pl.M1 + p.P) - 1e-9), g.Mt1));
+    pl.nl[1] = nice_size(std::max((int)std::ceil(p.s_l * (pl.M2 + p.P) - 1e-9), g.Mt2));
+    if (std::max({pl.n0[0], pl.n0[1], pl.nl[0], pl.nl[1]}) > 4096)
+        return SE1P_ERR_UNSUPPORTED;
+
+    // slabs n3 = 0 .. M3/2 (eq. upsamplings)
+    pl.nslab = p.M3 / 2 + 1;
+    pl.slabs.resize(pl.nslab);
+    std::map<int, int> twoff;   // length -> offset
+    long long twn = 0;
+    auto tw_of = [&](int n) {
+        auto it = twoff.find(n);
+        if (it != twoff.end()) return it->second;
+        twoff[n] = (int)twn;
+        twn += n;
+        return (int)(twn - n);
+    };
+    if (!factorize(p.M3, pl.dz)) return SE1P_ERR_UNSUPPORTED;
+    pl.dz.twoff = tw_of(p.M3);
+    long long off = 0;
+    for (int s = 0; s < pl.nslab; ++s) {
+        SlabDesc& sd = pl.slabs[s];
+        sd.n3 = s;
+        if (s == 0) { sd.n1 = pl.n0[0]; sd.n2 = pl.n0[1]; }
+        else if (s <= p.n_l) { sd.n1 = pl.nl[0]; sd.n2 = pl.nl[1]; }
+        else { sd.n1 = g.Mt1; sd.n2 = g.Mt2; }
+        sd.pad_ = 0;
+        sd.off = off;
+        off += (long long)g.Mt1 * sd.n2;
+        sd.pref = 4.0 * kPi * g.h * g.h * g.h * pl.cg * pl.cg /
+                  ((double)p.M3 * sd.n1 * sd.n2);
+        if (!factorize(sd.n1, sd.d1) || !factorize(sd.n2, sd.d2))
+            return SE1P_ERR_UNSUPPORTED;
+        sd.d1.twoff = tw_of(sd.n1);
+        sd.d2.twoff = tw_of(sd.n2);
+    }
+    pl.slab_elems = off;
+    pl.tw_elems = twn;
+
+    // LDS limits of the transform kernels
+    const size_t cs = 2 * pl.es;
+    int n1max = 0, n2max = 0;
+    for (auto& sd : pl.slabs) { n1max = std::max(n1max, sd.n1); n2max = std::max(n2max, sd.n2); }
+    const size_t lds_z = 2 * (kZfftCols / 2) * (size_t)(p.M3 + 1) * cs;
+    const size_t lds_r = 2 * 4 * (size_t)n2max * cs;
+    const size_t lds_c = 2 * 4 * (size_t)(n1max + 1) * cs;
+    if (std::max({lds_z, lds_r, lds_c}) > 160 * 1024) return SE1P_ERR_UNSUPPORTED;
+
+    // ---- workspace layout ----
+    const long long N = std::max<long long>(n_max, 1);
+    std::vector<std::pair<void**, size_t>> req;
+    auto add = [&](void** ptr, size_t bytes) { req.push_back({ptr, (bytes + 255) & ~size_t(255)}); };
+    add((void**)&pl.key_lex, N * 4);
+    add((void**)&pl.key_blk, N * 4);
+    add((void**)&pl.slot_lex, N * 4);
+    add((void**)&pl.slot_blk, N * 4);
+    add((void**)&pl.cnt_lex, (pl.bg.ncell_lex + 1) * 4);
+    add((void**)&pl.cnt_blk, (pl.bg.ncell_blk + 1) * 4);
+    for (int k = 0; k < 4; ++k) { add((void**)&pl.lex_i[k], N * 4); add((void**)&pl.blk_i[k], N * 4); }
+    add((void**)&pl.lex_i[4], (pl.bg.ncell_lex + 1) * 4);
+    add((void**)&pl.blk_i[4], (pl.bg.ncell_blk + 1) * 4);
+    for (int k = 0; k < 4; ++k) { add(&pl.lex_f[k], N * pl.es); add(&pl.blk_f[k], N * pl.es); }
+    pl.scan_bytes = std::max(scan_temp_bytes(pl.bg.ncell_lex + 1),
+                             scan_temp_bytes(pl.bg.ncell_blk + 1)) + 256;
+    add(&pl.scan_tmp, pl.scan_bytes);
+    const int PW = p.P + 2 * kPad;
+    add(&pl.wz, (size_t)N * p.P * pl.es);
+    add(&pl.wxp, (size_t)N * PW * pl.es);
+    add(&pl.wyq, (size_t)N * PW * pl.es);
+    pl.pstride = (long long)p.M3 * g.ncol;
+    add(&pl.Hpart, (size_t)pl.KP * pl.pstride * pl.es);
+    add(&pl.Fz, (size_t)pl.nslab * g.ncol * cs);
+    add(&pl.G, (size_t)pl.slab_elems * cs);
+    add(&pl.Ht, (size_t)pl.pstride * pl.es);
+    add(&pl.S0, (size_t)pl.n0[0] * pl.n0[1] * pl.es);
+    add(&pl.tw, (size_t)pl.tw_elems * cs);
+    add((void**)&pl.d_slabs, pl.slabs.size() * sizeof(SlabDesc));
+    add(&pl.phiF, N * pl.es);
+    add(&pl.EF, 3 * N * pl.es);
+    add(&pl.phiR, N * pl.es);
+    add(&pl.ER, 3 * N * pl.es);
+    pl.nblk_comb = (int)((N + 255) / 256);
+    add((void**)&pl.partials, (size_t)pl.nblk_comb * 8);
+    add((void**)&pl.flag, 256);
+    add((void**)&pl.qsum, 256);
+    size_t total = 0;
+    for (auto& r : req) total += r.second;
+    pl.ws_bytes = total;
+    if (hipMalloc(&pl.base, total) != hipSuccess) {
+        pl.base = nullptr;
+        (void)hipGetLastError();
+        return SE1P_ERR_NOMEM;
+    }
+    char* cur = (char*)pl.base;
+    for (auto& r : req) { *r.first = cur; cur += r.second; }
+
+    // ---- tables: twiddles, slab descriptors, FP64 scaling of slab 0 ----
+    std::vector<double> twd(2 * pl.tw_elems);
+    for (auto& kv : twoff) {
+        const int n = kv.first, o = kv.second;
+        for (int k = 0; k < n; ++k) {
+            const double ang = -2.0 * kPi * (double)k / (double)n;
+            twd[2 * (o + k)] = std::cos(ang);
+            twd[2 * (o + k) + 1] = std::sin(ang);
+        }
+    }
+    const int a0 = pl.n0[0], b0 = pl.n0[1];
+    std::vector<double> s0(a0 * (size_t)b0);
+    const SlabDesc& z0 = pl.slabs[0];
+    for (int kx = 0; kx < a0; ++kx) {
+        const int fx = (kx <= a0 / 2) ? kx : kx - a0;
+        const double k1 = 2.0 * kPi * fx / (a0 * g.h);
+        for (int ky = 0; ky < b0; ++ky) {
+            const int fy = (ky <= b0 / 2) ? ky : ky - b0;
+            const double k2 = 2.0 * kPi * fy / (b0 * g.h);
+            const double kap2 = k1 * k1 + k2 * k2;
+            double v = z0.pref * std::exp(-(1.0 - g.eta) * kap2 / (4.0 * p.xi * p.xi)) *
+                       G_R(std::sqrt(kap2), pl.R);
+            if (kx == 0 && ky == 0) v = 0.0;   // (kappa, k3) = (0, 0)
+            s0[(size_t)kx * b0 + ky] = v;
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (pl.prec == SE1P_FP64) {
+        e = hipMemcpy(pl.tw, twd.data(), twd.size() * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(pl.S0, s0.data(), s0.size() * 8, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> twf(twd.begin(), twd.end()), s0f(s0.begin(), s0.end());
+        e = hipMemcpy(pl.tw, twf.data(), twf.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(pl.S0, s0f.data(), s0f.size() * 4, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(pl.d_slabs, pl.slabs.data(), pl.slabs.size() * sizeof(SlabDesc),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) return SE1P_ERR_HIP;
+    return SE1P_OK;
+}
+
+template <typename T>
+int run_bin(se1p_plan& pl, long long N, const void* x, const void* q) {
+    DevParticles<T> lex = particles<T>(pl, true), blk = particles<T>(pl, false);
+    return launch_bin<T>((const T*)x, (const T*)q, N, pl.g, pl.bg, pl.key_lex,
+                         pl.key_blk, pl.slot_lex, pl.slot_blk, pl.cnt_lex,
+                         pl.cnt_blk, lex, blk, pl.scan_tmp, pl.scan_bytes,
+                         pl.stream);
+}
+
+template <typename T>
+int run_spread(se1p_plan& pl, long long N) {
+    DevParticles<T> lex = particles<T>(pl, true);
+    return launch_spread<T>(lex, N, pl.g, pl.CZ, pl.KP, (T*)pl.wz, (T*)pl.wxp,
+                            (T*)pl.wyq, (T*)pl.Hpart, pl.pstride, pl.stream);
+}
+
+template <typename T>
+int run_kspace(se1p_plan& pl, const T* Hin, int KP, T in_scale, T out_scale,
+               T* Ht) {
+    return launch_kspace<T>(Hin, KP, pl.pstride, in_scale, pl.g, pl.nslab,
+                            pl.d_slabs, pl.slabs.data(), pl.dz,
+                            (const cplx<T>*)pl.tw, (const T*)pl.S0,
+                            (cplx<T>*)pl.Fz, (cplx<T>*)pl.G, out_scale, Ht,
+                            pl.stream);
+}
+
+template <typename T>
+int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
+             void* phi, void* efield, double* energy, unsigned flags) {
+    int rc;
+    if ((rc = run_bin<T>(pl, N, x, q))) return rc;
+    unsigned comp = flags & SE1P_ALL;
+    if (comp & SE1P_KSPACE) {
+        if ((rc = run_spread<T>(pl, N))) return rc;
+        if ((rc = run_kspace<T>(pl, (const T*)pl.Hpart, pl.KP, (T)1, (T)1, (T*)pl.Ht))) return rc;
+        DevParticles<T> blk = particles<T>(pl, false);
+        if ((rc = launch_gather<T>((const T*)pl.Ht, blk, N, pl.g, pl.bg, (T)1,
+                                   (T*)pl.phiF, (T*)pl.EF, pl.stream)))
+            return rc;
+    }
+    if ((comp & SE1P_REAL) && pl.prm.rc > 0.0) {
+        DevParticles<T> lex = particles<T>(pl, true);
+        if ((rc = launch_realspace<T>(lex, N, pl.g, pl.prm.xi, pl.prm.rc,
+                                      (T*)pl.phiR, (T*)pl.ER, pl.stream)))
+            return rc;
+    } else {
+        comp &= ~SE1P_REAL;
+    }
+    const double self_c = 2.0 * pl.prm.xi / std::sqrt(kPi);
+    const int nb = (int)((N + 255) / 256);
+    return launch_combine<T>(N, (const T*)q, (const T*)pl.phiF, (const T*)pl.EF,
+                             (const T*)pl.phiR, (const T*)pl.ER, self_c, comp,
+                             (T*)phi, (T*)efield, pl.partials, nb, energy,
+                             pl.stream);
+}
+
+template <typename T>
+int run_check(se1p_plan& pl, long long N, const void* x, const void* q,
+              bool neutral) {
+    if (hipMemsetAsync(pl.flag, 0, 4, pl.stream) != hipSuccess) return SE1P_ERR_HIP;
+    if (hipMemsetAsync(pl.qsum, 0, 16, pl.stream) != hipSuccess) return SE1P_ERR_HIP;
+    int rc = launch_check<T>((const T*)x, (const T*)q, N, pl.prm.box[0],
+                             pl.prm.box[1], pl.flag, pl.qsum, pl.stream);
+    if (rc) return rc;
+    int hflag = 0;
+    double hq[2] = {0, 0};
+    if (hipMemcpyAsync(&hflag, pl.flag, 4, hipMemcpyDeviceToHost, pl.stream) != hipSuccess)
+        return SE1P_ERR_HIP;
+    if (hipMemcpyAsync(hq, pl.qsum, 16, hipMemcpyDeviceToHost, pl.stream) != hipSuccess)
+        return SE1P_ERR_HIP;
+    if (hipStreamSynchronize(pl.stream) != hipSuccess) return SE1P_ERR_HIP;
+    if (hflag) return SE1P_ERR_OUT_OF_BOX;
+    if (neutral && std::fabs(hq[0]) > 1e-10 * hq[1]) return SE1P_ERR_NONNEUTRAL;
+    return SE1P_OK;
+}
+
+int set_device(const se1p_plan* pl) {
+    return hipSetDevice(pl->device) == hipSuccess ? SE1P_OK : SE1P_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* se1p_error_string(int code) {
+    switch (code) {
+        case SE1P_OK: return "success";
+        case SE1P_ERR_ARG: return "invalid argument";
+        case SE1P_ERR_PARAM: return "inconsistent method parameters";
+        case SE1P_ERR_NONNEUTRAL: return "charges are not neutral";
+        case SE1P_ERR_OUT_OF_BOX: return "position outside the box in a free direction";
+        case SE1P_ERR_HIP: return "HIP runtime error";
+        case SE1P_ERR_NOMEM: return "device allocation failed";
+        case SE1P_ERR_TOO_MANY: return "more particles than the plan allows";
+        case SE1P_ERR_UNSUPPORTED: return "unsupported parameter combination";
+        default: return "unknown error";
+    }
+}
+
+const char* se1p_version(void) { return "se1p-mi355x 0.1.0 (gfx950)"; }
+
+int se1p_suggest_params(double tol, const double box[3], long long N, double Q,
+                        double xi_in, int M3_in, int P_in, int n_l_in,
+                        int precision, se1p_params* out) {
+    if (!box || !out || !(tol > 0.0) || !(tol < 1.0) || N < 1 || !(Q > 0.0))
+        return SE1P_ERR_ARG;
+    if (precision != SE1P_FP64 && precision != SE1P_FP32) return SE1P_ERR_ARG;
+    for (int d = 0; d < 3; ++d)
+        if (!(box[d] > 0.0)) return SE1P_ERR_ARG;
+    const double L = box[2];
+    const double V = box[0] * box[1] * box[2];
+    se1p_params p{};
+    p.box[0] = box[0]; p.box[1] = box[1]; p.box[2] = box[2];
+    p.precision = precision;
+    // Fourier truncation estimate (eq. trunc_error_estimate_fourier)
+    auto errF = [&](double xi, double kinf) {
+        return xi / (kPi * kPi) * std::pow(kinf, -1.5) * std::sqrt(Q) *
+               std::exp(-std::pow(kPi * kinf / (xi * L), 2));
+    };
+    if (M3_in > 0) {
+        p.M3 = M3_in + (M3_in & 1);
+        const double kinf = p.M3 / 2.0;
+        if (xi_in > 0.0) {
+            p.xi = xi_in;
+        } else {
+            double lo = 1e-3 / L, hi = 1e3 / L;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = std::sqrt(lo * hi);
+                if (errF(mid, kinf) < tol) lo = mid; else hi = mid;
+            }
+            p.xi = lo;
+        }
+    } else {
+        if (!(xi_in > 0.0)) return SE1P_ERR_ARG;
+        p.xi = xi_in;
+        // eq. kinf
+        const double D = 4.0 / (3.0 * L * L) * std::pow(Q / kPi, 2.0 / 3.0);
+        const double kinf = std::sqrt(3.0) * L * p.xi / (2.0 * kPi) *
+                            std::sqrt(lambert_w(D / std::pow(p.xi * tol * tol, 2.0 / 3.0)));
+        p.M3 = 2 * (int)std::ceil(kinf);
+        if (p.M3 < 8) p.M3 = 8;
+    }
+    // eq. rc with V for L^3
+    const double C = Q / (2.0 * V * p.xi * tol * tol);
+    p.rc = 1.0 / (2.0 * p.xi) * std::sqrt(3.0 * lambert_w(4.0 / 3.0 * std::pow(C, 2.0 / 3.0)));
+    // eq. approximation_error_oneterm with A = sqrt(Q xi L) / L
+    if (P_in > 0) {
+        p.P = P_in;
+    } else {
+        const double A = std::sqrt(Q * p.xi * L) / L;
+        int P = (int)std::ceil(2.0 * std::log(std::max(A / tol, 1.0)) / (kShapeC * kShapeC * kPi));
+        P += P & 1;
+        p.P = std::min(std::max(P, 4), kMaxP);
+    }
+    if (p.P > p.M3) p.P = p.M3 - (p.M3 & 1);
+    // eq. choose_sl generalised: exp(-2 pi s_l Lt / L3) < tol
+    const double h = L / p.M3;
+    const double Lt = std::min(std::ceil(box[0] / h - 1e-9), std::ceil(box[1] / h - 1e-9)) * h + p.P * h;
+    p.s_l = std::max(1.0, std::log(1.0 / tol) * L / (2.0 * kPi * Lt));
+    // eq. choose_nl: M ~ 10 n_l
+    p.n_l = (n_l_in >= 0) ? n_l_in : std::max(1, (int)std::lround(p.M3 / 10.0));
+    p.s0 = 1.0 + std::sqrt(2.0);
+    *out = p;
+    return check_params(p);
+}
+
+int se1p_plan_create(const se1p_params* params, long long n_max, void* stream,
+                     se1p_plan** out) {
+    if (!params || !out || n_max < 1 || n_max > (1LL << 30)) return SE1P_ERR_ARG;
+    *out = nullptr;
+    int rc = check_params(*params);
+    if (rc) return rc;
+    se1p_plan* pl = new (std::nothrow) se1p_plan();
+    if (!pl) return SE1P_ERR_NOMEM;
+    if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return SE1P_ERR_HIP; }
+    pl->stream = (hipStream_t)stream;
+    rc = build_plan(*pl, *params, n_max);
+    if (rc) {
+        if (pl->base) (void)hipFree(pl->base);
+        delete pl;
+        return rc;
+    }
+    *out = pl;
+    return SE1P_OK;
+}
+
+int se1p_plan_destroy(se1p_plan* plan) {
+    if (!plan) return SE1P_ERR_ARG;
+    int rc = SE1P_OK;
+    if (set_device(plan)) rc = SE1P_ERR_HIP;
+    if (hipStreamSynchronize(plan->stream) != hipSuccess) rc = SE1P_ERR_HIP;
+    if (plan->base && hipFree(plan->base) != hipSuccess) rc = SE1P_ERR_HIP;
+    delete plan;
+    return rc;
+}
+
+int se1p_plan_get_info(const se1p_plan* pl, se1p_plan_info* info) {
+    if (!pl || !info) return SE1P_ERR_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->h = pl->g.h;
+    info->eta = pl->g.eta;
+    info->R = pl->R;
+    info->M[0] = pl->M1;
+    info->M[1] = pl->M2;
+    info->Mt[0] = pl->g.Mt1;
+    info->Mt[1] = pl->g.Mt2;
+    info->M3 = pl->g.M3;
+    info->P = pl->g.P;
+    info->n0[0] = pl->n0[0];
+    info->n0[1] = pl->n0[1];
+    info->nl[0] = pl->nl[0];
+    info->nl[1] = pl->nl[1];
+    info->n_l = pl->prm.n_l;
+    info->nslab = pl->nslab;
+    info->precision = pl->prec;
+    info->n_max = pl->n_max;
+    info->workspace_bytes = pl->ws_bytes;
+    return SE1P_OK;
+}
+
+int se1p_set_stream(se1p_plan* plan, void* stream) {
+    if (!plan) return SE1P_ERR_ARG;
+    plan->stream = (hipStream_t)stream;
+    return SE1P_OK;
+}
+
+int se1p_eval(se1p_plan* pl, long long N, const void* x, const void* q,
+              void* phi, void* efield, double* energy, unsigned flags) {
+    if (!pl || !x || !q) return SE1P_ERR_ARG;
+    if (flags & ~(SE1P_ALL | SE1P_CHECK_INPUT | SE1P_NO_NEUTRAL)) return SE1P_ERR_ARG;
+    if ((flags & SE1P_ALL) == 0) return SE1P_ERR_ARG;
+    if (N < 1) return SE1P_ERR_ARG;
+    if (N > pl->n_max) return SE1P_ERR_TOO_MANY;
+    if ((flags & SE1P_REAL) && !(pl->prm.rc > 0.0)) return SE1P_ERR_PARAM;
+    if (set_device(pl)) return SE1P_ERR_HIP;
+    if (flags & SE1P_CHECK_INPUT) {
+        const bool neutral = !(flags & SE1P_NO_NEUTRAL);
+        int rc = (pl->prec == SE1P_FP64) ? run_check<double>(*pl, N, x, q, neutral)
+                                         : run_check<float>(*pl, N, x, q, neutral);
+        if (rc) return rc;
+    }
+    if (pl->prec == SE1P_FP64)
+        return run_eval<double>(*pl, N, x, q, phi, efield, energy, flags);
+    return run_eval<float>(*pl, N, x, q, phi, efield, energy, flags);
+}
+
+int se1p_spread(se1p_plan* pl, long long N, const void* x, const void* q,
+                void* grid) {
+    if (!pl || !x || !q || !grid) return SE1P_ERR_ARG;
+    if (N < 1) return SE1P_ERR_ARG;
+    if (N > pl->n_max) return SE1P_ERR_TOO_MANY;
+    if (set_device(pl)) return SE1P_ERR_HIP;
+    int rc;
+    const long long n = pl->pstride;
+    if (pl->prec == SE1P_FP64) {
+        if ((rc = run_bin<double>(*pl, N, x, q))) return rc;
+        if ((rc = run_spread<double>(*pl, N))) return rc;
+        return launch_reduce_partials<double>((const double*)pl->Hpart, pl->KP, n, n,
+                                              pl->cg, (double*)grid, pl->stream);
+    }
+    if ((rc = run_bin<float>(*pl, N, x, q))) return rc;
+    if ((rc = run_spread<float>(*pl, N))) return rc;
+    return launch_reduce_partials<float>((const float*)pl->Hpart, pl->KP, n, n,
+                                         (float)pl->cg, (float*)grid, pl->stream);
+}
+
+int se1p_kspace_solve(se1p_plan* pl, const void* grid_in, void* grid_out) {
+    if (!pl || !grid_in || !grid_out) return SE1P_ERR_ARG;
+    if (set_device(pl)) return SE1P_ERR_HIP;
+    const double h3 = pl->g.h * pl->g.h * pl->g.h;
+    const double in_s = 1.0 / pl->cg;
+    const double out_s = 1.0 / (4.0 * kPi * h3 * pl->cg);
+    if (pl->prec == SE1P_FP64)
+        return run_kspace<double>(*pl, (const double*)grid_in, 1, in_s, out_s,
+                                  (double*)grid_out);
+    return run_kspace<float>(*pl, (const float*)grid_in, 1, (float)in_s,
+                             (float)out_s, (float*)grid_out);
+}
+
+int se1p_gather(se1p_plan* pl, long long N, const void* x, const void* grid,
+                void* phi, void* efield) {
+    if (!pl || !x || !grid) return SE1P_ERR_ARG;
+    if (N < 1) return SE1P_ERR_ARG;
+    if (N > pl->n_max) return SE1P_ERR_TOO_MANY;
+    if (set_device(pl)) return SE1P_ERR_HIP;
+    const double h3 = pl->g.h * pl->g.h * pl->g.h;
+    const double sc = 4.0 * kPi * h3 * pl->cg;
+    int rc;
+    // binning needs charges only for the sorted copies; reuse x as a dummy
+    // charge array is not possible (stride differs), so bin with phiF as q.
+    if (pl->prec == SE1P_FP64) {
+        if ((rc = run_bin<double>(*pl, N, x, pl->phiF))) return rc;
+        DevParticles<double> blk = particles<double>(*pl, false);
+        return launch_gather<double>((const double*)grid, blk, N, pl->g, pl->bg, sc,
+                                     (double*)phi, (double*)efield, pl->stream);
+    }
+    if ((rc = run_bin<float>(*pl, N, x, pl->phiF))) return rc;
+    DevParticles<float> blk = particles<float>(*pl, false);
+    return launch_gather<float>((const float*)grid, blk, N, pl->g, pl->bg, (float)sc,
+                                (float*)phi, (float*)efield, pl->stream);
+}
+
+}  // extern "C"

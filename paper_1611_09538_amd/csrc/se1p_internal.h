@@ -1,0 +1,116 @@
+// se1p_internal.h -- shared between the host planner and the HIP kernels of
+// the SE1P library.  Not part of the public C ABI (include/se1p.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace se1p {
+
+constexpr int kMaxRad = 16;      // radix passes per FFT length
+constexpr int kSpreadTile = 8;   // spread tile: 8 x 8 (x, y) pencils per wave
+constexpr int kPad = 7;          // zero padding on each side of the x/y spread weights
+constexpr int kZfftCols = 32;    // columns per block in the z transforms
+constexpr int kMaxP = 32;
+
+// One 1D FFT length: radices in pass order and the offset of its twiddle
+// table exp(-2 pi i k / n), k = 0..n-1, inside the plan's twiddle array.
+struct FftDesc {
+    int n;
+    int nrad;
+    int twoff;
+    int rad[kMaxRad];
+};
+
+// Per-slab (n3 = 0 .. M3/2) description of the adaptive transform: padded
+// sizes (eq. upsamplings), FFT descriptors and the slab's offset (complex
+// elements) into the padded-slab workspace.
+struct SlabDesc {
+    int n1, n2;        // padded FFT lengths along x and y
+    int n3;            // mode index
+    int pad_;
+    long long off;     // complex elements
+    double pref;       // 4 pi h^3 cg^2 / (M3 n1 n2)
+    FftDesc d1, d2;
+};
+
+// Geometry passed by value to kernels.
+struct Geo {
+    double h, inv_h, L3, alpha, eta, xi;
+    int M1, M2, M3, P;
+    int Mt1, Mt2;
+    long long ncol;    // Mt1 * Mt2
+};
+
+// Binning: particle cells in two orders.
+//   lex order   (cz, cx, cy)  -- spreading and the real-space sum
+//   block order blocks of BZ x BX x BY cells, lexicographic inside  -- gather
+struct BinGeo {
+    int BX, BY, BZ;
+    int nbx, nby, nbz;
+    int cpb;              // cells per block
+    long long ncell_lex;  // M3 * M1 * M2
+    long long ncell_blk;  // nbz * nbx * nby * cpb
+};
+
+template <typename T> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+template <typename T> using cplx = typename cplx_t<T>::type;
+
+// ---- launchers (implemented in se1p_kernels.hip) ---------------------------
+template <typename T>
+struct DevParticles {        // sorted copies of the particles in one order
+    T* x; T* y; T* z; T* q;  // z wrapped into [0, L3)
+    int* cx; int* cy; int* cz;
+    int* perm;               // sorted position -> input index
+    int* start;              // cell starts, size ncell + 1
+};
+
+template <typename T>
+int launch_bin(const T* x_in, const T* q_in, long long N, const Geo& g,
+               const BinGeo& bg, int* key_lex, int* key_blk, int* slot_lex,
+               int* slot_blk, int* cnt_lex, int* cnt_blk,
+               DevParticles<T>& lex, DevParticles<T>& blk, void* scan_tmp,
+               size_t scan_tmp_bytes, hipStream_t s);
+
+template <typename T>
+int launch_spread(const DevParticles<T>& lex, long long N, const Geo& g,
+                  int CZ, int KP, T* wz, T* wxp, T* wyq, T* Hpart,
+                  long long pstride, hipStream_t s);
+
+template <typename T>
+int launch_reduce_partials(const T* Hpart, int KP, long long pstride,
+                           long long n, T scale, T* out, hipStream_t s);
+
+template <typename T>
+int launch_kspace(const T* Hin, int KP, long long pstride, T in_scale,
+                  const Geo& g, int nslab, const SlabDesc* d_slabs,
+                  const SlabDesc* h_slabs, const FftDesc& dz,
+                  const cplx<T>* tw, const T* S0, cplx<T>* Fz, cplx<T>* G,
+                  T out_scale, T* Ht, hipStream_t s);
+
+template <typename T>
+int launch_gather(const T* Ht, const DevParticles<T>& blk, long long N,
+                  const Geo& g, const BinGeo& bg, T scale, T* phi_out,
+                  T* E_out, hipStream_t s);
+
+template <typename T>
+int launch_realspace(const DevParticles<T>& lex, long long N, const Geo& g,
+                     double xi, double rc, T* phi_out, T* E_out,
+                     hipStream_t s);
+
+template <typename T>
+int launch_combine(long long N, const T* q_in, const T* phiF, const T* EF,
+                   const T* phiR, const T* ER, double self_c, unsigned flags,
+                   T* phi, T* E, double* partials, int nblk, double* energy,
+                   hipStream_t s);
+
+template <typename T>
+int launch_check(const T* x, const T* q, long long N, double L1, double L2,
+                 int* flag, double* qsum, hipStream_t s);
+
+int launch_fill_int(int* p, long long n, int v, hipStream_t s);
+
+}  // namespace se1p

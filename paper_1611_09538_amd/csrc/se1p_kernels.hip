@@ -1,0 +1,1109 @@
+// se1p_kernels.hip -- HIP kernels of the SE1P k-space pipeline for gfx950.
+//
+// Pipeline (Algorithm 1 of the paper):
+//   bin        counting sort of the particles by cell in two orders
+//   spread     step 2, eq. spread_1p: owner-computes gridding, one wave per
+//              8 x 8 (x, y) pencil tile sweeping a chunk of z cells with the
+//              z-support in registers; per-particle z weights arrive as
+//              wave-uniform (scalar) loads, x/y weights are per lane
+//   kspace     steps 3-5: z FFT (real, two columns per complex transform),
+//              per-slab zero-padded row FFTs, fused column FFT -> scaling
+//              (eq. scale_1p with G of eq. G_kappa_k) -> inverse column FFT,
+//              inverse row FFTs, inverse z FFT; Stockham FFTs in LDS
+//   gather     step 6 (eq. se1p_complete_discretized) and its analytic
+//              gradient (eq. force_se1p): one lane per particle, grid rows
+//              read as wave-uniform scalar loads
+//   realspace  eq. ewald1p_real / eq. force_real over the cell list
+//   combine    totals, self term (eq. ewald1p_self), energy 1/2 sum q phi
+//
+// Grid layout: real grids are [z][x][y] (y fastest); z-spectra [n3][x][y].
+// The Gaussian normalisation and all transform normalisations are folded
+// into the scaling factors, so spread and gather use exp(-alpha d^2).
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include "se1p_internal.h"
+
+namespace se1p {
+
+namespace {
+
+// ------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int imod(int a, int m) {
+    int r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+template <typename T> __device__ __forceinline__ T dexp(T v);
+template <> __device__ __forceinline__ double dexp<double>(double v) { return exp(v); }
+template <> __device__ __forceinline__ float dexp<float>(float v) { return __expf(v); }
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    cplx<T> r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {  // a * conj(b)
+    cplx<T> r;
+    r.x = a.x * b.x + a.y * b.y;
+    r.y = a.y * b.x - a.x * b.y;
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) {
+    cplx<T> r; r.x = a.x + b.x; r.y = a.y + b.y; return r;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) {
+    cplx<T> r; r.x = a.x - b.x; r.y = a.y - b.y; return r;
+}
+// multiply by i*s (s = +1 or -1)
+template <typename T>
+__device__ __forceinline__ cplx<T> cmuli(cplx<T> a, T s) {
+    cplx<T> r; r.x = -s * a.y; r.y = s * a.x; return r;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) {
+    cplx<T> r; r.x = a.x * s; r.y = a.y * s; return r;
+}
+
+// ------------------------------------------------------------------------
+// Stockham FFT in LDS, block-cooperative, mixed radix 2/3/4/5.
+// 'batch' transforms of length n start at a + b*stride; b is scratch of the
+// same shape.  Returns the buffer holding the result.  sgn = -1 forward
+// (exp(-2 pi i jk/n)), +1 inverse (unnormalised).
+// ------------------------------------------------------------------------
+template <typename T>
+__device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int batch, int stride,
+                            const FftDesc& d, const cplx<T>* __restrict__ tw,
+                            int sgn) {
+    const int n = d.n;
+    const T s = (T)sgn;
+    int Ns = 1;
+    for (int p = 0; p < d.nrad; ++p) {
+        const int R = d.rad[p];
+        const int nR = n / R;
+        const int tstep = n / (Ns * R);
+        const int total = batch * nR;
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            const int bi = t / nR;
+            const int j = t - bi * nR;
+            const cplx<T>* src = a + (long)bi * stride;
+            cplx<T>* dst = b + (long)bi * stride;
+            const int k = j % Ns;
+            const int base = (j / Ns) * Ns * R + k;
+            const int tb = k * tstep;
+            if (R == 4) {
+                cplx<T> v0 = src[j], v1 = src[j + nR], v2 = src[j + 2 * nR], v3 = src[j + 3 * nR];
+                if (k) {
+                    cplx<T> w1 = tw[tb], w2 = tw[2 * tb], w3 = tw[3 * tb];
+                    if (sgn < 0) { v1 = cmul<T>(v1, w1); v2 = cmul<T>(v2, w2); v3 = cmul<T>(v3, w3); }
+                    else { v1 = cmulc<T>(v1, w1); v2 = cmulc<T>(v2, w2); v3 = cmulc<T>(v3, w3); }
+                }
+                cplx<T> a0 = cadd<T>(v0, v2), a1 = csub<T>(v0, v2);
+                cplx<T> b0 = cadd<T>(v1, v3), b1 = cmuli<T>(csub<T>(v1, v3), s);
+                dst[base] = cadd<T>(a0, b0);
+                dst[base + Ns] = cadd<T>(a1, b1);
+                dst[base + 2 * Ns] = csub<T>(a0, b0);
+                dst[base + 3 * Ns] = csub<T>(a1, b1);
+            } else if (R == 2) {
+                cplx<T> v0 = src[j], v1 = src[j + nR];
+                if (k) {
+                    cplx<T> w1 = tw[tb];
+                    v1 = (sgn < 0) ? cmul<T>(v1, w1) : cmulc<T>(v1, w1);
+                }
+                dst[base] = cadd<T>(v0, v1);
+                dst[base + Ns] = csub<T>(v0, v1);
+            } else if (R == 3) {
+                cplx<T> v0 = src[j], v1 = src[j + nR], v2 = src[j + 2 * nR];
+                if (k) {
+                    cplx<T> w1 = tw[tb], w2 = tw[2 * tb];
+                    if (sgn < 0) { v1 = cmul<T>(v1, w1); v2 = cmul<T>(v2, w2); }
+                    else { v1 = cmulc<T>(v1, w1); v2 = cmulc<T>(v2, w2); }
+                }
+                const T c1 = (T)-0.5;
+                const T s1 = (T)0.86602540378443864676372317075294;
+                cplx<T> t = cadd<T>(v1, v2), u = csub<T>(v1, v2);
+                cplx<T> m;
+                m.x = v0.x + c1 * t.x;
+                m.y = v0.y + c1 * t.y;
+                cplx<T> r = cmuli<T>(cscale<T>(u, s1), s);
+                dst[base] = cadd<T>(v0, t);
+                dst[base + Ns] = cadd<T>(m, r);
+                dst[base + 2 * Ns] = csub<T>(m, r);
+            } else {  // R == 5
+                cplx<T> v0 = src[j], v1 = src[j + nR], v2 = src[j + 2 * nR],
+                        v3 = src[j + 3 * nR], v4 = src[j + 4 * nR];
+                if (k) {
+                    cplx<T> w1 = tw[tb], w2 = tw[2 * tb], w3 = tw[3 * tb], w4 = tw[4 * tb];
+                    if (sgn < 0) {
+                        v1 = cmul<T>(v1, w1); v2 = cmul<T>(v2, w2);
+                        v3 = cmul<T>(v3, w3); v4 = cmul<T>(v4, w4);
+                    } else {
+                        v1 = cmulc<T>(v1, w1); v2 = cmulc<T>(v2, w2);
+                        v3 = cmulc<T>(v3, w3); v4 = cmulc<T>(v4, w4);
+                    }
+                }
+                const T c1 = (T)0.30901699437494742410229341718282;
+                const T c2 = (T)-0.80901699437494742410229341718282;
+                const T s1 = (T)0.95105651629515357211643933337938;
+                const T s2 = (T)0.58778525229247312916870595463907;
+                cplx<T> t1 = cadd<T>(v1, v4), t2 = cadd<T>(v2, v3);
+                cplx<T> u1 = csub<T>(v1, v4), u2 = csub<T>(v2, v3);
+                cplx<T> m1, m2, r1, r2;
+                m1.x = v0.x + c1 * t1.x + c2 * t2.x;
+                m1.y = v0.y + c1 * t1.y + c2 * t2.y;
+                m2.x = v0.x + c2 * t1.x + c1 * t2.x;
+                m2.y = v0.y + c2 * t1.y + c1 * t2.y;
+                cplx<T> q1, q2;
+                q1.x = s1 * u1.x + s2 * u2.x;
+                q1.y = s1 * u1.y + s2 * u2.y;
+                q2.x = s2 * u1.x - s1 * u2.x;
+                q2.y = s2 * u1.y - s1 * u2.y;
+                r1 = cmuli<T>(q1, s);
+                r2 = cmuli<T>(q2, s);
+                cplx<T> y0;
+                y0.x = v0.x + t1.x + t2.x;
+                y0.y = v0.y + t1.y + t2.y;
+                dst[base] = y0;
+                dst[base + Ns] = cadd<T>(m1, r1);
+                dst[base + 4 * Ns] = csub<T>(m1, r1);
+                dst[base + 2 * Ns] = cadd<T>(m2, r2);
+                dst[base + 3 * Ns] = csub<T>(m2, r2);
+            }
+        }
+        __syncthreads();
+        cplx<T>* tmp = a; a = b; b = tmp;
+        Ns *= R;
+    }
+    return a;
+}
+
+// ------------------------------------------------------------------------
+// binning
+// ------------------------------------------------------------------------
+__global__ void fill_int_kernel(int* __restrict__ p, long long n, int v) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <typename T>
+__device__ __forceinline__ void cell_of(T x, T y, T z, const Geo& g, T& zw,
+                                        int& cx, int& cy, int& cz) {
+    const T L3 = (T)g.L3;
+    const T h = (T)g.h;
+    zw = z - L3 * floor(z / L3);
+    if (!(zw < L3)) zw = (T)0;       // also maps NaN to 0
+    if (zw < (T)0) zw = (T)0;
+    cx = (int)floor(x / h);
+    cy = (int)floor(y / h);
+    cz = (int)floor(zw / h);
+    cx = min(max(cx, 0), g.M1 - 1);
+    cy = min(max(cy, 0), g.M2 - 1);
+    cz = min(max(cz, 0), g.M3 - 1);
+}
+
+template <typename T>
+__global__ void bin_keys_kernel(const T* __restrict__ xin, long long N, Geo g,
+                                BinGeo bg, int* __restrict__ key_lex,
+                                int* __restrict__ key_blk,
+                                int* __restrict__ slot_lex,
+                                int* __restrict__ slot_blk,
+                                int* __restrict__ cnt_lex,
+                                int* __restrict__ cnt_blk) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    T zw;
+    int cx, cy, cz;
+    cell_of<T>(xin[3 * i], xin[3 * i + 1], xin[3 * i + 2], g, zw, cx, cy, cz);
+    const int kl = (cz * g.M1 + cx) * g.M2 + cy;
+    const int bz = cz / bg.BZ, iz = cz - bz * bg.BZ;
+    const int bx = cx / bg.BX, ix = cx - bx * bg.BX;
+    const int by = cy / bg.BY, iy = cy - by * bg.BY;
+    const int b = (bz * bg.nbx + bx) * bg.nby + by;
+    const int kb = b * bg.cpb + (iz * bg.BX + ix) * bg.BY + iy;
+    key_lex[i] = kl;
+    key_blk[i] = kb;
+    slot_lex[i] = atomicAdd(&cnt_lex[kl], 1);
+    slot_blk[i] = atomicAdd(&cnt_blk[kb], 1);
+}
+
+__global__ void bin_scatter_kernel(long long N, const int* __restrict__ key,
+                                   const int* __restrict__ slot,
+                                   const int* __restrict__ start,
+                                   int* __restrict__ perm) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    perm[start[key[i]] + slot[i]] = (int)i;
+}
+
+// Sort each cell's entries by input index so the particle order (and the
+// floating-point summation order downstream) does not depend on the order
+// the atomics were served in.
+__global__ void bin_sort_cells_kernel(long long ncell,
+                                      const int* __restrict__ start,
+                                      int* __restrict__ perm) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int s = start[c], e = start[c + 1];
+    for (int i = s + 1; i < e; ++i) {
+        int v = perm[i];
+        int j = i - 1;
+        while (j >= s && perm[j] > v) {
+            perm[j + 1] = perm[j];
+            --j;
+        }
+        perm[j + 1] = v;
+    }
+}
+
+template <typename T>
+__global__ void bin_gather_kernel(const T* __restrict__ xin,
+                                  const T* __restrict__ qin, long long N,
+                                  Geo g, DevParticles<T> o) {
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int i = o.perm[p];
+    const T x = xin[3 * (long long)i], y = xin[3 * (long long)i + 1];
+    T zw;
+    int cx, cy, cz;
+    cell_of<T>(x, y, xin[3 * (long long)i + 2], g, zw, cx, cy, cz);
+    o.x[p] = x;
+    o.y[p] = y;
+    o.z[p] = zw;
+    o.q[p] = qin[i];
+    o.cx[p] = cx;
+    o.cy[p] = cy;
+    o.cz[p] = cz;
+}
+
+// ------------------------------------------------------------------------
+// spreading (step 2)
+// ------------------------------------------------------------------------
+// Per particle (lex order): z weights wz[P] (wave-uniform in the spread
+// kernel) and zero-padded x weights wxp[P + 2 kPad], q * y weights wyq.
+template <typename T, int P>
+__global__ void spread_weights_kernel(DevParticles<T> lx, long long N, Geo g,
+                                      T* __restrict__ wz, T* __restrict__ wxp,
+                                      T* __restrict__ wyq) {
+    constexpr int PW = P + 2 * kPad;
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const T h = (T)g.h, a = (T)g.alpha;
+    const T x = lx.x[p], y = lx.y[p], z = lx.z[p], q = lx.q[p];
+    const int cx = lx.cx[p], cy = lx.cy[p], cz = lx.cz[p];
+    for (int k = 0; k < PW; ++k) {
+        const int u = k - kPad;
+        const bool in = (u >= 0) && (u < P);
+        const T dx = x - (T)(cx + 1 + u - P / 2) * h;
+        const T dy = y - (T)(cy + 1 + u - P / 2) * h;
+        wxp[p * PW + k] = in ? dexp<T>(-a * dx * dx) : (T)0;
+        wyq[p * PW + k] = in ? q * dexp<T>(-a * dy * dy) : (T)0;
+    }
+    for (int d = 0; d < P; ++d) {
+        const T dz = z - (T)(cz - P / 2 + 1 + d) * h;
+        wz[p * P + d] = dexp<T>(-a * dz * dz);
+    }
+}
+
+// One wave owns the (x, y) pencils [X0, X0+8) x [Y0, Y0+8) and the z cells
+// [cz0, cz0+CZ).  acc[d] holds grid point z = cz - P/2 + 1 + d while cell cz
+// is processed; after cell cz the point z = cz - P/2 + 1 is final for this
+// chunk and is written out.  Chunk jc writes KP*CZ consecutive z planes
+// (mod M3) of partial grid jc % KP; with M3/CZ a multiple of KP, the chunks
+// of one partial grid tile the period exactly, so every partial grid is
+// fully written and the partial grids only need summing.
+template <typename T, int P>
+__global__ __launch_bounds__(64) void spread_kernel(
+    const T* __restrict__ wz, const T* __restrict__ wxp,
+    const T* __restrict__ wyq, const int* __restrict__ pcy,
+    const int* __restrict__ cstart, T* __restrict__ Hpart,
+    long long pstride, Geo g, int CZ, int KP) {
+    constexpr int PW = P + 2 * kPad;
+    const int lane = threadIdx.x;
+    const int X0 = blockIdx.x * kSpreadTile;
+    const int Y0 = blockIdx.y * kSpreadTile;
+    const int jc = blockIdx.z;
+    const int lx = X0 + (lane >> 3);
+    const int ly = Y0 + (lane & 7);
+    const int cz0 = jc * CZ;
+    const int cxlo = max(0, X0 - P), cxhi = min(g.M1 - 1, X0 + kSpreadTile - 2);
+    const int cylo = max(0, Y0 - P), cyhi = min(g.M2 - 1, Y0 + kSpreadTile - 2);
+    const bool writer = (lx < g.Mt1) && (ly < g.Mt2);
+    T* __restrict__ out = Hpart + (long long)(jc % KP) * pstride +
+                          (long long)lx * g.Mt2 + ly;
+    const int zstart = cz0 - P / 2 + 1;
+
+    T acc[P];
+#pragma unroll
+    for (int d = 0; d < P; ++d) acc[d] = (T)0;
+
+    for (int ci = 0; ci < CZ; ++ci) {
+        const int cz = cz0 + ci;
+        if (cxlo <= cxhi && cylo <= cyhi) {
+            for (int cx = cxlo; cx <= cxhi; ++cx) {
+                const long long cb = ((long long)cz * g.M1 + cx) * g.M2;
+                const int s = cstart[cb + cylo];
+                const int e = cstart[cb + cyhi + 1];
+                const int offx = lx - (cx + 1) + kPad;
+                int p = s;
+                for (; p + 1 < e; p += 2) {
+                    const int cyA = pcy[p], cyB = pcy[p + 1];
+                    const T cA = wxp[(long long)p * PW + offx] *
+                                 wyq[(long long)p * PW + ly - (cyA + 1) + kPad];
+                    const T cB = wxp[(long long)(p + 1) * PW + offx] *
+                                 wyq[(long long)(p + 1) * PW + ly - (cyB + 1) + kPad];
+                    const T* __restrict__ zA = wz + (long long)p * P;
+                    const T* __restrict__ zB = zA + P;
+#pragma unroll
+                    for (int d = 0; d < P; ++d) acc[d] = fma(cA, zA[d], acc[d]);
+#pragma unroll
+                    for (int d = 0; d < P; ++d) acc[d] = fma(cB, zB[d], acc[d]);
+                }
+                if (p < e) {
+                    const int cyA = pcy[p];
+                    const T cA = wxp[(long long)p * PW + offx] *
+                                 wyq[(long long)p * PW + ly - (cyA + 1) + kPad];
+                    const T* __restrict__ zA = wz + (long long)p * P;
+#pragma unroll
+                    for (int d = 0; d < P; ++d) acc[d] = fma(cA, zA[d], acc[d]);
+                }
+            }
+        }
+        // plane zstart + ci is final
+        if (writer) out[(long long)imod(zstart + ci, g.M3) * g.ncol] = acc[0];
+#pragma unroll
+        for (int d = 0; d < P - 1; ++d) acc[d] = acc[d + 1];
+        acc[P - 1] = (T)0;
+    }
+    // remaining planes of this chunk's KP*CZ-plane window
+    const int base = zstart + CZ;
+#pragma unroll
+    for (int d = 0; d < P - 1; ++d) {
+        if (writer) out[(long long)imod(base + d, g.M3) * g.ncol] = acc[d];
+    }
+    const int tail = KP * CZ - CZ;
+    for (int d = P - 1; d < tail; ++d) {
+        if (writer) out[(long long)imod(base + d, g.M3) * g.ncol] = (T)0;
+    }
+}
+
+template <typename T>
+__global__ void reduce_partials_kernel(const T* __restrict__ Hp, int KP,
+                                       long long pstride, long long n, T scale,
+                                       T* __restrict__ out) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T v = 0;
+    for (int k = 0; k < KP; ++k) v += Hp[k * pstride + i];
+    out[i] = v * scale;
+}
+
+// ------------------------------------------------------------------------
+// k-space: z transforms
+// ------------------------------------------------------------------------
+// Forward real FFT along z of kZfftCols columns per block; columns 2t and
+// 2t+1 share one complex transform.  Sums the KP partial grids on load.
+template <typename T>
+__global__ __launch_bounds__(256) void zfft_kernel(
+    const T* __restrict__ H, int KP, long long pstride, T in_scale,
+    cplx<T>* __restrict__ Fz, Geo g, FftDesc d,
+    const cplx<T>* __restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int M3 = g.M3;
+    const int stride = M3 + 1;
+    constexpr int CB = kZfftCols;
+    cplx<T>* B = A + (CB / 2) * stride;
+    const long long ncol = g.ncol;
+    const long long c0 = (long long)blockIdx.x * CB;
+    for (int idx = threadIdx.x; idx < CB * M3; idx += blockDim.x) {
+        const int z = idx / CB, c = idx - z * CB;
+        const long long col = c0 + c;
+        T v = 0;
+        if (col < ncol) {
+            const T* src = H + (long long)z * ncol + col;
+            for (int k = 0; k < KP; ++k) v += src[k * pstride];
+            v *= in_scale;
+        }
+        T* at = reinterpret_cast<T*>(&A[(c >> 1) * stride + z]);
+        at[c & 1] = v;
+    }
+    __syncthreads();
+    cplx<T>* X = fft_lds<T>(A, B, CB / 2, stride, d, tw + d.twoff, -1);
+    const int nh = M3 / 2 + 1;
+    for (int idx = threadIdx.x; idx < nh * CB; idx += blockDim.x) {
+        const int n3 = idx / CB, c = idx - n3 * CB;
+        const long long col = c0 + c;
+        if (col >= ncol) continue;
+        const cplx<T> Xk = X[(c >> 1) * stride + n3];
+        const cplx<T> Xm = X[(c >> 1) * stride + (n3 == 0 ? 0 : M3 - n3)];
+        cplx<T> r;
+        if ((c & 1) == 0) {
+            r.x = (T)0.5 * (Xk.x + Xm.x);
+            r.y = (T)0.5 * (Xk.y - Xm.y);
+        } else {
+            r.x = (T)0.5 * (Xk.y + Xm.y);
+            r.y = (T)-0.5 * (Xk.x - Xm.x);
+        }
+        Fz[(long long)n3 * ncol + col] = r;
+    }
+}
+
+// Inverse real FFT along z; writes Ht[z][col] * out_scale.
+template <typename T>
+__global__ __launch_bounds__(256) void zifft_kernel(
+    const cplx<T>* __restrict__ Fz, T out_scale, T* __restrict__ Ht, Geo g,
+    FftDesc d, const cplx<T>* __restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int M3 = g.M3;
+    const int stride = M3 + 1;
+    constexpr int CB = kZfftCols;
+    cplx<T>* B = A + (CB / 2) * stride;
+    const long long ncol = g.ncol;
+    const long long c0 = (long long)blockIdx.x * CB;
+    const int half = M3 / 2;
+    for (int idx = threadIdx.x; idx < M3 * (CB / 2); idx += blockDim.x) {
+        const int k = idx / (CB / 2), t = idx - k * (CB / 2);
+        const long long ca = c0 + 2 * t, cbb = ca + 1;
+        const int src = (k <= half) ? k : M3 - k;
+        const bool cj = k > half;
+        cplx<T> fa, fb;
+        fa.x = fa.y = fb.x = fb.y = (T)0;
+        if (ca < ncol) fa = Fz[(long long)src * ncol + ca];
+        if (cbb < ncol) fb = Fz[(long long)src * ncol + cbb];
+        if (k == 0 || k == half) { fa.y = (T)0; fb.y = (T)0; }
+        if (cj) { fa.y = -fa.y; fb.y = -fb.y; }
+        cplx<T> z;
+        z.x = fa.x - fb.y;
+        z.y = fa.y + fb.x;
+        A[t * stride + k] = z;
+    }
+    __syncthreads();
+    cplx<T>* X = fft_lds<T>(A, B, CB / 2, stride, d, tw + d.twoff, +1);
+    for (int idx = threadIdx.x; idx < M3 * CB; idx += blockDim.x) {
+        const int z = idx / CB, c = idx - z * CB;
+        const long long col = c0 + c;
+        if (col >= ncol) continue;
+        const cplx<T> v = X[(c >> 1) * stride + z];
+        Ht[(long long)z * ncol + col] = ((c & 1) ? v.y : v.x) * out_scale;
+    }
+}
+
+// ------------------------------------------------------------------------
+// k-space: slab transforms (eq. upsamplings: per-slab padded sizes)
+// ------------------------------------------------------------------------
+constexpr int kRowsPerBlock = 4;
+
+// Zero-padded forward FFT along y of the Mt1 rows of slab blockIdx.y.
+template <typename T>
+__global__ __launch_bounds__(256) void rowfwd_kernel(
+    const cplx<T>* __restrict__ Fz, cplx<T>* __restrict__ G,
+    const SlabDesc* __restrict__ slabs, Geo g,
+    const cplx<T>* __restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const SlabDesc sd = slabs[blockIdx.y];
+    const int n2 = sd.n2;
+    const int x0 = blockIdx.x * kRowsPerBlock;
+    if (x0 >= g.Mt1) return;
+    const int nr = min(kRowsPerBlock, g.Mt1 - x0);
+    cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* B = A + kRowsPerBlock * n2;
+    const cplx<T>* src = Fz + (long long)blockIdx.y * g.ncol;
+    for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
+        const int r = idx / n2, j = idx - r * n2;
+        cplx<T> v;
+        v.x = v.y = (T)0;
+        if (j < g.Mt2) v = src[(long long)(x0 + r) * g.Mt2 + j];
+        A[r * n2 + j] = v;
+    }
+    __syncthreads();
+    cplx<T>* X = fft_lds<T>(A, B, nr, n2, sd.d2, tw + sd.d2.twoff, -1);
+    cplx<T>* dst = G + sd.off;
+    for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
+        const int r = idx / n2, j = idx - r * n2;
+        dst[(long long)(x0 + r) * n2 + j] = X[r * n2 + j];
+    }
+}
+
+// Scaling factor (eq. scale_1p with G of eq. G_kappa_k), all constants and
+// transform normalisations included.  Slab 0 uses the FP64 host table S0.
+template <typename T>
+__device__ __forceinline__ T slab_scale(const SlabDesc& sd, int kx, int ky,
+                                        const Geo& g,
+                                        const T* __restrict__ S0) {
+    if (sd.n3 == 0) return S0[(long long)kx * sd.n2 + ky];
+    const double twopi = 6.283185307179586476925286766559;
+    const int fx = (kx <= sd.n1 / 2) ? kx : kx - sd.n1;
+    const int fy = (ky <= sd.n2 / 2) ? ky : ky - sd.n2;
+    const double k1 = twopi * fx / (sd.n1 * g.h);
+    const double k2 = twopi * fy / (sd.n2 * g.h);
+    const double k3 = twopi * sd.n3 / g.L3;
+    const double k2s = k1 * k1 + k2 * k2 + k3 * k3;
+    if constexpr (sizeof(T) == 8) {
+        return (T)(sd.pref * exp(-(1.0 - g.eta) * k2s / (4.0 * g.xi * g.xi)) / k2s);
+    } else {
+        const float e = (float)(-(1.0 - g.eta) * k2s / (4.0 * g.xi * g.xi));
+        return (float)sd.pref * __expf(e) / (float)k2s;
+    }
+}
+
+constexpr int kColsPerBlock = 4;
+
+// Fused column pass: zero-padded FFT along x, scaling, inverse FFT along x,
+// restriction to the first Mt1 rows, for kColsPerBlock columns ky.
+template <typename T>
+__global__ __launch_bounds__(256) void cols_kernel(
+    cplx<T>* __restrict__ G, const SlabDesc* __restrict__ slabs, Geo g,
+    const cplx<T>* __restrict__ tw, const T* __restrict__ S0) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const SlabDesc sd = slabs[blockIdx.y];
+    const int n1 = sd.n1, n2 = sd.n2;
+    const int k0 = blockIdx.x * kColsPerBlock;
+    if (k0 >= n2) return;
+    const int nc = min(kColsPerBlock, n2 - k0);
+    const int stride = n1 + 1;
+    cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* B = A + kColsPerBlock * stride;
+    cplx<T>* base = G + sd.off;
+    for (int idx = threadIdx.x; idx < n1 * kColsPerBlock; idx += blockDim.x) {
+        const int x = idx / kColsPerBlock, c = idx - x * kColsPerBlock;
+        cplx<T> v;
+        v.x = v.y = (T)0;
+        if (x < g.Mt1 && c < nc) v = base[(long long)x * n2 + k0 + c];
+        A[c * stride + x] = v;
+    }
+    __syncthreads();
+    cplx<T>* X = fft_lds<T>(A, B, kColsPerBlock, stride, sd.d1,
+                            tw + sd.d1.twoff, -1);
+    cplx<T>* Y = (X == A) ? B : A;
+    for (int idx = threadIdx.x; idx < n1 * kColsPerBlock; idx += blockDim.x) {
+        const int c = idx / n1, kx = idx - c * n1;
+        const T s = (c < nc) ? slab_scale<T>(sd, kx, k0 + c, g, S0) : (T)0;
+        X[c * stride + kx] = cscale<T>(X[c * stride + kx], s);
+    }
+    __syncthreads();
+    cplx<T>* Z = fft_lds<T>(X, Y, kColsPerBlock, stride, sd.d1,
+                            tw + sd.d1.twoff, +1);
+    for (int idx = threadIdx.x; idx < g.Mt1 * kColsPerBlock; idx += blockDim.x) {
+        const int x = idx / kColsPerBlock, c = idx - x * kColsPerBlock;
+        if (c < nc) base[(long long)x * n2 + k0 + c] = Z[c * stride + x];
+    }
+}
+
+// Inverse FFT along y, restriction to the first Mt2 columns.
+template <typename T>
+__global__ __launch_bounds__(256) void rowinv_kernel(
+    const cplx<T>* __restrict__ G, cplx<T>* __restrict__ Fz,
+    const SlabDesc* __restrict__ slabs, Geo g,
+    const cplx<T>* __restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const SlabDesc sd = slabs[blockIdx.y];
+    const int n2 = sd.n2;
+    const int x0 = blockIdx.x * kRowsPerBlock;
+    if (x0 >= g.Mt1) return;
+    const int nr = min(kRowsPerBlock, g.Mt1 - x0);
+    cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* B = A + kRowsPerBlock * n2;
+    const cplx<T>* src = G + sd.off;
+    for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
+        const int r = idx / n2, j = idx - r * n2;
+        A[r * n2 + j] = src[(long long)(x0 + r) * n2 + j];
+    }
+    __syncthreads();
+    cplx<T>* X = fft_lds<T>(A, B, nr, n2, sd.d2, tw + sd.d2.twoff, +1);
+    cplx<T>* dst = Fz + (long long)blockIdx.y * g.ncol;
+    for (int idx = threadIdx.x; idx < nr * g.Mt2; idx += blockDim.x) {
+        const int r = idx / g.Mt2, j = idx - r * g.Mt2;
+        dst[(long long)(x0 + r) * g.Mt2 + j] = X[r * n2 + j];
+    }
+}
+
+// ------------------------------------------------------------------------
+// gather (step 6) and its gradient
+// ------------------------------------------------------------------------
+// One wave per block of BX x BY x BZ cells, lanes = particles (chunks of 64).
+// The union of the particles' supports is swept plane by plane (z) and row
+// by row (x); each row of UY = BY + P - 1 grid values along y is wave-uniform
+// and reaches the lanes through scalar loads.  The lane's own y weights are
+// kept in registers; x and z weights are recomputed per row.
+template <typename T, int P, int BY>
+__global__ __launch_bounds__(64) void gather_kernel(
+    const T* __restrict__ Ht, const T* __restrict__ px,
+    const T* __restrict__ py, const T* __restrict__ pz,
+    const int* __restrict__ pcx, const int* __restrict__ pcy,
+    const int* __restrict__ pcz, const int* __restrict__ perm,
+    const int* __restrict__ cstart, Geo g, BinGeo bg, T scale,
+    T* __restrict__ phi_out, T* __restrict__ E_out) {
+    constexpr int UY = P + BY - 1;
+    const int b = blockIdx.x;
+    const int byk = b % bg.nby;
+    const int tmp = b / bg.nby;
+    const int bxk = tmp % bg.nbx;
+    const int bzk = tmp / bg.nbx;
+    const int s = cstart[(long long)b * bg.cpb];
+    const int e = cstart[(long long)(b + 1) * bg.cpb];
+    if (s >= e) return;
+    const int X0u = bxk * bg.BX + 1;  // array index of the union start in x
+    const int Y0u = byk * BY + 1;
+    const int Ux = bg.BX + P - 1;
+    const int Uz = bg.BZ + P - 1;
+    const int zl0 = bzk * bg.BZ - P / 2 + 1;  // z index of the union start
+    const T h = (T)g.h, a = (T)g.alpha;
+
+    for (int c0 = s; c0 < e; c0 += 64) {
+        const int p = c0 + (int)threadIdx.x;
+        const bool act = p < e;
+        const int pp = act ? p : e - 1;
+        const T x = px[pp], y = py[pp], z = pz[pp];
+        const int ox = pcx[pp] - bxk * bg.BX;
+        const int oy = pcy[pp] - byk * BY;
+        const int oz = pcz[pp] - bzk * bg.BZ;
+
+        T wy[UY], ty[UY];
+#pragma unroll
+        for (int u = 0; u < UY; ++u) {
+            const int dd = u - oy;
+            const T dy = y - (T)(Y0u + u - P / 2) * h;
+            const T w = (act && dd >= 0 && dd < P) ? dexp<T>(-a * dy * dy) : (T)0;
+            wy[u] = w;
+            ty[u] = dy * w;
+        }
+        T phi = 0, ex = 0, ey = 0, ez = 0;
+        for (int uz = 0; uz < Uz; ++uz) {
+            const int dzi = uz - oz;
+            const bool zin = act && dzi >= 0 && dzi < P;
+            if (!__any(zin)) continue;
+            const T dz = z - (T)(zl0 + uz) * h;
+            const T wzv = zin ? dexp<T>(-a * dz * dz) : (T)0;
+            const T tz = dz * wzv;
+            const T* __restrict__ plane =
+                Ht + (long long)imod(zl0 + uz, g.M3) * g.ncol +
+                (long long)X0u * g.Mt2 + Y0u;
+            for (int ux = 0; ux < Ux; ++ux) {
+                const int dxi = ux - ox;
+                const bool xin = zin && dxi >= 0 && dxi < P;
+                if (!__any(xin)) continue;
+                const T dx = x - (T)(X0u + ux - P / 2) * h;
+                const T wx = xin ? dexp<T>(-a * dx * dx) : (T)0;
+                const T* __restrict__ row = plane + (long long)ux * g.Mt2;
+                T sy = 0, sty = 0;
+#pragma unroll
+                for (int u = 0; u < UY; ++u) {
+                    const T hv = row[u];
+                    sy = fma(wy[u], hv, sy);
+                    sty = fma(ty[u], hv, sty);
+                }
+                const T wxz = wx * wzv;
+                phi = fma(wxz, sy, phi);
+                ey = fma(wxz, sty, ey);
+                ex = fma(dx * wxz, sy, ex);
+                ez = fma(wx * tz, sy, ez);
+            }
+        }
+        if (act) {
+            const long long o = perm[p];
+            if (phi_out) phi_out[o] = scale * phi;
+            if (E_out) {
+                const T f = scale * (T)2 * a;
+                E_out[3 * o] = f * ex;
+                E_out[3 * o + 1] = f * ey;
+                E_out[3 * o + 2] = f * ez;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// real-space sum over the cell list (lex order, cells of size h)
+// ------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void realspace_kernel(
+    DevParticles<T> lx, long long N, Geo g, T xi, T rc, int R,
+    T* __restrict__ phi_out, T* __restrict__ E_out) {
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const T x = lx.x[p], y = lx.y[p], z = lx.z[p];
+    const int cx = lx.cx[p], cy = lx.cy[p], cz = lx.cz[p];
+    const T rc2 = rc * rc;
+    const T c_erf = (T)1.1283791670955125738961589031215 * xi;  // 2 xi / sqrt(pi)
+    const T xi2 = xi * xi;
+    const T L3 = (T)g.L3;
+    T phi = 0, ex = 0, ey = 0, ez = 0;
+    const int ylo = max(0, cy - R), yhi = min(g.M2 - 1, cy + R);
+    const int xlo = max(0, cx - R), xhi = min(g.M1 - 1, cx + R);
+    for (int dzc = -R; dzc <= R; ++dzc) {
+        const int czu = cz + dzc;
+        const int czw = imod(czu, g.M3);
+        const int img = (czu - czw) / g.M3;
+        const T shift = (T)img * L3;
+        for (int cxn = xlo; cxn <= xhi; ++cxn) {
+            const long long cb = ((long long)czw * g.M1 + cxn) * g.M2;
+            const int s = lx.start[cb + ylo];
+            const int e = lx.start[cb + yhi + 1];
+            for (int n = s; n < e; ++n) {
+                if (n == p && img == 0) continue;
+                const T dx = x - lx.x[n];
+                const T dy = y - lx.y[n];
+                const T dz = z - (lx.z[n] + shift);
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 > rc2) continue;
+                const T r = sqrt(r2);
+                const T qn = lx.q[n];
+                const T ec = erfc(xi * r) / r;
+                phi += qn * ec;
+                const T f = qn * (ec + c_erf * exp(-xi2 * r2)) / r2;
+                ex += f * dx;
+                ey += f * dy;
+                ez += f * dz;
+            }
+        }
+    }
+    const long long o = lx.perm[p];
+    phi_out[o] = phi;
+    E_out[3 * o] = ex;
+    E_out[3 * o + 1] = ey;
+    E_out[3 * o + 2] = ez;
+}
+
+// ------------------------------------------------------------------------
+// totals and energy
+// ------------------------------------------------------------------------
+constexpr int kCombineThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kCombineThreads) void combine_kernel(
+    long long N, const T* __restrict__ q, const T* __restrict__ phiF,
+    const T* __restrict__ EF, const T* __restrict__ phiR,
+    const T* __restrict__ ER, double self_c, unsigned flags,
+    T* __restrict__ phi, T* __restrict__ E, double* __restrict__ partials) {
+    __shared__ double red[kCombineThreads];
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double u = 0.0;
+    if (i < N) {
+        const T qi = q[i];
+        T ph = 0;
+        if (flags & 1u) ph += phiF[i];
+        if (flags & 2u) ph += phiR[i];
+        if (flags & 4u) ph += (T)(-self_c) * qi;
+        if (phi) phi[i] = ph;
+        if (E) {
+            for (int d = 0; d < 3; ++d) {
+                T v = 0;
+                if (flags & 1u) v += EF[3 * i + d];
+                if (flags & 2u) v += ER[3 * i + d];
+                E[3 * i + d] = v;
+            }
+        }
+        u = (double)qi * (double)ph;
+    }
+    red[threadIdx.x] = u;
+    __syncthreads();
+    for (int w = kCombineThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void energy_final_kernel(
+    const double* __restrict__ partials, int n, double* __restrict__ energy) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += partials[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *energy = 0.5 * red[0];
+}
+
+// ------------------------------------------------------------------------
+// optional input validation (device side)
+// ------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void check_kernel(
+    const T* __restrict__ x, const T* __restrict__ q, long long N, double L1,
+    double L2, int* __restrict__ flag, double* __restrict__ qsum) {
+    __shared__ double r1[256], r2[256];
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (i < N) {
+        const double xx = x[3 * i], yy = x[3 * i + 1], zz = x[3 * i + 2];
+        const bool ok = (xx >= 0.0) && (xx < L1) && (yy >= 0.0) && (yy < L2) &&
+                        (zz == zz) && (zz - zz == 0.0);
+        if (!ok) atomicOr(flag, 1);
+        a = q[i];
+        b = fabs((double)q[i]);
+    }
+    r1[threadIdx.x] = a;
+    r2[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            r1[threadIdx.x] += r1[threadIdx.x + w];
+            r2[threadIdx.x] += r2[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&qsum[0], r1[0]);
+        atomicAdd(&qsum[1], r2[0]);
+    }
+}
+
+inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ==========================================================================
+// launchers
+// ==========================================================================
+#define SE1P_CHECK_LAUNCH()                                  \
+    do {                                                     \
+        if (hipGetLastError() != hipSuccess) return -5;      \
+    } while (0)
+
+int launch_fill_int(int* p, long long n, int v, hipStream_t s) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, p,
+                       n, v);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+template <typename T>
+int launch_bin(const T* x_in, const T* q_in, long long N, const Geo& g,
+               const BinGeo& bg, int* key_lex, int* key_blk, int* slot_lex,
+               int* slot_blk, int* cnt_lex, int* cnt_blk,
+               DevParticles<T>& lex, DevParticles<T>& blk, void* scan_tmp,
+               size_t scan_tmp_bytes, hipStream_t s) {
+    int rc;
+    if ((rc = launch_fill_int(cnt_lex, bg.ncell_lex + 1, 0, s))) return rc;
+    if ((rc = launch_fill_int(cnt_blk, bg.ncell_blk + 1, 0, s))) return rc;
+    hipLaunchKernelGGL(bin_keys_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0, s,
+                       x_in, N, g, bg, key_lex, key_blk, slot_lex, slot_blk,
+                       cnt_lex, cnt_blk);
+    SE1P_CHECK_LAUNCH();
+    size_t tb = scan_tmp_bytes;
+    if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb, cnt_lex, lex.start,
+                                         (int)(bg.ncell_lex + 1), s) != hipSuccess)
+        return -5;
+    tb = scan_tmp_bytes;
+    if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb, cnt_blk, blk.start,
+                                         (int)(bg.ncell_blk + 1), s) != hipSuccess)
+        return -5;
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(N, 256)), dim3(256), 0, s,
+                       N, key_lex, slot_lex, lex.start, lex.perm);
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(N, 256)), dim3(256), 0, s,
+                       N, key_blk, slot_blk, blk.start, blk.perm);
+    hipLaunchKernelGGL(bin_sort_cells_kernel, dim3(nblk(bg.ncell_lex, 256)),
+                       dim3(256), 0, s, bg.ncell_lex, lex.start, lex.perm);
+    hipLaunchKernelGGL(bin_sort_cells_kernel, dim3(nblk(bg.ncell_blk, 256)),
+                       dim3(256), 0, s, bg.ncell_blk, blk.start, blk.perm);
+    hipLaunchKernelGGL(bin_gather_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0,
+                       s, x_in, q_in, N, g, lex);
+    hipLaunchKernelGGL(bin_gather_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0,
+                       s, x_in, q_in, N, g, blk);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+template <typename T, int P>
+static int spread_p(const DevParticles<T>& lex, long long N, const Geo& g,
+                    int CZ, int KP, T* wz, T* wxp, T* wyq, T* Hpart,
+                    long long pstride, hipStream_t s) {
+    hipLaunchKernelGGL((spread_weights_kernel<T, P>), dim3(nblk(N, 128)),
+                       dim3(128), 0, s, lex, N, g, wz, wxp, wyq);
+    SE1P_CHECK_LAUNCH();
+    dim3 grid((g.Mt1 + kSpreadTile - 1) / kSpreadTile,
+              (g.Mt2 + kSpreadTile - 1) / kSpreadTile, g.M3 / CZ);
+    hipLaunchKernelGGL((spread_kernel<T, P>), grid, dim3(64), 0, s, wz, wxp,
+                       wyq, lex.cy, lex.start, Hpart, pstride, g, CZ, KP);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+#define SE1P_P_CASES(F) \
+    F(4) F(6) F(8) F(10) F(12) F(14) F(16) F(18) F(20) F(22) F(24) F(26) F(28) F(30) F(32)
+
+template <typename T>
+int launch_spread(const DevParticles<T>& lex, long long N, const Geo& g,
+                  int CZ, int KP, T* wz, T* wxp, T* wyq, T* Hpart,
+                  long long pstride, hipStream_t s) {
+    switch (g.P) {
+#define SE1P_SPREAD_CASE(PP) \
+    case PP: return spread_p<T, PP>(lex, N, g, CZ, KP, wz, wxp, wyq, Hpart, pstride, s);
+        SE1P_P_CASES(SE1P_SPREAD_CASE)
+#undef SE1P_SPREAD_CASE
+        default: return -8;
+    }
+}
+
+template <typename T>
+int launch_reduce_partials(const T* Hpart, int KP, long long pstride,
+                           long long n, T scale, T* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partials_kernel<T>, dim3(nblk(n, 256)), dim3(256),
+                       0, s, Hpart, KP, pstride, n, scale, out);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+template <typename T>
+int launch_kspace(const T* Hin, int KP, long long pstride, T in_scale,
+                  const Geo& g, int nslab, const SlabDesc* d_slabs,
+                  const SlabDesc* h_slabs, const FftDesc& dz,
+                  const cplx<T>* tw, const T* S0, cplx<T>* Fz, cplx<T>* G,
+                  T out_scale, T* Ht, hipStream_t s) {
+    const size_t cs = sizeof(cplx<T>);
+    const unsigned ncb = (unsigned)((g.ncol + kZfftCols - 1) / kZfftCols);
+    const size_t zsm = 2 * (kZfftCols / 2) * (size_t)(g.M3 + 1) * cs;
+    hipLaunchKernelGGL(zfft_kernel<T>, dim3(ncb), dim3(256), zsm, s, Hin, KP,
+                       pstride, in_scale, Fz, g, dz, tw);
+    SE1P_CHECK_LAUNCH();
+    int n1max = 0, n2max = 0;
+    for (int i = 0; i < nslab; ++i) {
+        n1max = n1max > h_slabs[i].n1 ? n1max : h_slabs[i].n1;
+        n2max = n2max > h_slabs[i].n2 ? n2max : h_slabs[i].n2;
+    }
+    const size_t rsm = 2 * (size_t)kRowsPerBlock * n2max * cs;
+    dim3 rgrid((g.Mt1 + kRowsPerBlock - 1) / kRowsPerBlock, nslab);
+    hipLaunchKernelGGL(rowfwd_kernel<T>, rgrid, dim3(256), rsm, s, Fz, G,
+                       d_slabs, g, tw);
+    SE1P_CHECK_LAUNCH();
+    const size_t csm = 2 * (size_t)kColsPerBlock * (n1max + 1) * cs;
+    dim3 cgrid((n2max + kColsPerBlock - 1) / kColsPerBlock, nslab);
+    hipLaunchKernelGGL(cols_kernel<T>, cgrid, dim3(256), csm, s, G, d_slabs, g,
+                       tw, S0);
+    SE1P_CHECK_LAUNCH();
+    hipLaunchKernelGGL(rowinv_kernel<T>, rgrid, dim3(256), rsm, s, G, Fz,
+                       d_slabs, g, tw);
+    SE1P_CHECK_LAUNCH();
+    hipLaunchKernelGGL(zifft_kernel<T>, dim3(ncb), dim3(256), zsm, s, Fz,
+                       out_scale, Ht, g, dz, tw);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+template <typename T, int P, int BY>
+static int gather_pb(const T* Ht, const DevParticles<T>& blk, const Geo& g,
+                     const BinGeo& bg, T scale, T* phi_out, T* E_out,
+                     hipStream_t s) {
+    const unsigned nb = (unsigned)(bg.nbx * bg.nby * bg.nbz);
+    hipLaunchKernelGGL((gather_kernel<T, P, BY>), dim3(nb), dim3(64), 0, s, Ht,
+                       blk.x, blk.y, blk.z, blk.cx, blk.cy, blk.cz, blk.perm,
+                       blk.start, g, bg, scale, phi_out, E_out);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+template <typename T, int P>
+static int gather_p(const T* Ht, const DevParticles<T>& blk, const Geo& g,
+                    const BinGeo& bg, T scale, T* phi_out, T* E_out,
+                    hipStream_t s) {
+    switch (bg.BY) {
+        case 2: return gather_pb<T, P, 2>(Ht, blk, g, bg, scale, phi_out, E_out, s);
+        case 4: return gather_pb<T, P, 4>(Ht, blk, g, bg, scale, phi_out, E_out, s);
+        case 8: return gather_pb<T, P, 8>(Ht, blk, g, bg, scale, phi_out, E_out, s);
+        default: return -8;
+    }
+}
+
+template <typename T>
+int launch_gather(const T* Ht, const DevParticles<T>& blk, long long N,
+                  const Geo& g, const BinGeo& bg, T scale, T* phi_out,
+                  T* E_out, hipStream_t s) {
+    (void)N;
+    switch (g.P) {
+#define SE1P_GATHER_CASE(PP) \
+    case PP: return gather_p<T, PP>(Ht, blk, g, bg, scale, phi_out, E_out, s);
+        SE1P_P_CASES(SE1P_GATHER_CASE)
+#undef SE1P_GATHER_CASE
+        default: return -8;
+    }
+}
+
+template <typename T>
+int launch_realspace(const DevParticles<T>& lex, long long N, const Geo& g,
+                     double xi, double rc, T* phi_out, T* E_out,
+                     hipStream_t s) {
+    const int R = (int)ceil(rc / g.h);
+    hipLaunchKernelGGL(realspace_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0, s,
+                       lex, N, g, (T)xi, (T)rc, R, phi_out, E_out);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+template <typename T>
+int launch_combine(long long N, const T* q_in, const T* phiF, const T* EF,
+                   const T* phiR, const T* ER, double self_c, unsigned flags,
+                   T* phi, T* E, double* partials, int nblkc, double* energy,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel<T>, dim3(nblkc), dim3(kCombineThreads),
+                       0, s, N, q_in, phiF, EF, phiR, ER, self_c, flags, phi, E,
+                       partials);
+    SE1P_CHECK_LAUNCH();
+    if (energy) {
+        hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(256), 0, s,
+                           partials, nblkc, energy);
+        SE1P_CHECK_LAUNCH();
+    }
+    return 0;
+}
+
+template <typename T>
+int launch_check(const T* x, const T* q, long long N, double L1, double L2,
+                 int* flag, double* qsum, hipStream_t s) {
+    hipLaunchKernelGGL(check_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0, s, x,
+                       q, N, L1, L2, flag, qsum);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+// explicit instantiations
+#define SE1P_INST(T)                                                           \
+    template int launch_bin<T>(const T*, const T*, long long, const Geo&,       \
+                               const BinGeo&, int*, int*, int*, int*, int*,     \
+                               int*, DevParticles<T>&, DevParticles<T>&, void*, \
+                               size_t, hipStream_t);                            \
+    template int launch_spread<T>(const DevParticles<T>&, long long,           \
+                                  const Geo&, int, int, T*, T*, T*, T*,         \
+                                  long long, hipStream_t);                      \
+    template int launch_reduce_partials<T>(const T*, int, long long,           \
+                                           long long, T, T*, hipStream_t);      \
+    template int launch_kspace<T>(const T*, int, long long, T, const Geo&, int, \
+                                  const SlabDesc*, const SlabDesc*,             \
+                                  const FftDesc&, const cplx<T>*, const T*,     \
+                                  cplx<T>*, cplx<T>*, T, T*, hipStream_t);      \
+    template int launch_gather<T>(const T*, const DevParticles<T>&, long long, \
+                                  const Geo&, const BinGeo&, T, T*, T*,         \
+                                  hipStream_t);                                 \
+    template int launch_realspace<T>(const DevParticles<T>&, long long,        \
+                                     const Geo&, double, double, T*, T*,        \
+                                     hipStream_t);                              \
+    template int launch_combine<T>(long long, const T*, const T*, const T*,    \
+                                   const T*, const T*, double, unsigned, T*,    \
+                                   T*, double*, int, double*, hipStream_t);     \
+    template int launch_check<T>(const T*, const T*, long long, double, double, \
+                                 int*, double*, hipStream_t);
+
+SE1P_INST(double)
+SE1P_INST(float)
+
+// Temporary storage the scan needs for n ints.
+size_t scan_temp_bytes(long long n) {
+    size_t tb = 0;
+    hipcub::DeviceScan::ExclusiveSum(nullptr, tb, (int*)nullptr, (int*)nullptr,
+                                     (int)n, (hipStream_t)0);
+    return tb;
+}
+
+}  // namespace se1p
