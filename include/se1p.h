@@ -223,6 +223,21 @@ int se1p_kspace_solve(se1p_plan* plan, const void* grid_in, void* grid_out);
 int se1p_gather(se1p_plan* plan, long long N, const void* x,
                 const void* grid, void* phi, void* efield);
 
+/*
+ * Stage timing with HIP events recorded on the plan's stream around each
+ * stage of se1p_eval, for profiling.  Stages, in order:
+ *   0 binning, 1 spreading, 2 AFT + scaling + AIFT, 3 gathering,
+ *   4 real-space sum, 5 totals and energy.
+ * se1p_timing_enable(plan, 1) starts recording (and clears earlier
+ * records); 0 stops.  se1p_timing_read synchronises the plan's stream and
+ * writes the summed milliseconds of each stage over the recorded calls
+ * (ms_sum has SE1P_NSTAGE entries) and the number of calls; stages a call
+ * skipped contribute zero.  Up to 4096 calls are kept.
+ */
+#define SE1P_NSTAGE 6
+int se1p_timing_enable(se1p_plan* plan, int enable);
+int se1p_timing_read(se1p_plan* plan, double* ms_sum, int* ncalls);
+
 /* Human-readable text for an error code (static storage). */
 const char* se1p_error_string(int code);
 

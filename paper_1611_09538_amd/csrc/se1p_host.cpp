@@ -134,7 +134,23 @@ struct se1p_plan {
     int nblk_comb = 0;
     int* flag = nullptr;
     double* qsum = nullptr;
+
+    // stage timing: events[call][boundary], boundaries 0..SE1P_NSTAGE
+    int timing = 0;
+    int tcalls = 0;
+    std::vector<hipEvent_t> tev;
+    std::vector<unsigned char> tmask;   // stages run per call
 };
+
+namespace {
+constexpr int kTimingMaxCalls = 4096;
+
+void tmark(se1p_plan& pl, int boundary) {
+    if (!pl.timing || pl.tcalls >= kTimingMaxCalls) return;
+    const size_t k = (size_t)pl.tcalls * (SE1P_NSTAGE + 1) + boundary;
+    if (k < pl.tev.size()) (void)hipEventRecord(pl.tev[k], pl.stream);
+}
+}  // namespace
 
 namespace {
 
@@ -434,30 +450,51 @@ template <typename T>
 int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
              void* phi, void* efield, double* energy, unsigned flags) {
     int rc;
+    unsigned char mask = 0;
+    tmark(pl, 0);
     if ((rc = run_bin<T>(pl, N, x, q))) return rc;
+    mask |= 1;
+    tmark(pl, 1);
     unsigned comp = flags & SE1P_ALL;
     if (comp & SE1P_KSPACE) {
         if ((rc = run_spread<T>(pl, N))) return rc;
+        tmark(pl, 2);
         if ((rc = run_kspace<T>(pl, (const T*)pl.Hpart, pl.KP, (T)1, (T)1, (T*)pl.Ht))) return rc;
+        tmark(pl, 3);
         DevParticles<T> blk = particles<T>(pl, false);
         if ((rc = launch_gather<T>((const T*)pl.Ht, blk, N, pl.g, pl.bg, (T)1,
                                    (T*)pl.phiF, (T*)pl.EF, pl.stream)))
             return rc;
+        mask |= 2 | 4 | 8;
+    } else {
+        tmark(pl, 2);
+        tmark(pl, 3);
     }
+    tmark(pl, 4);
     if ((comp & SE1P_REAL) && pl.prm.rc > 0.0) {
         DevParticles<T> lex = particles<T>(pl, true);
         if ((rc = launch_realspace<T>(lex, N, pl.g, pl.prm.xi, pl.prm.rc,
                                       (T*)pl.phiR, (T*)pl.ER, pl.stream)))
             return rc;
+        mask |= 16;
     } else {
         comp &= ~SE1P_REAL;
     }
+    tmark(pl, 5);
     const double self_c = 2.0 * pl.prm.xi / std::sqrt(kPi);
     const int nb = (int)((N + 255) / 256);
-    return launch_combine<T>(N, (const T*)q, (const T*)pl.phiF, (const T*)pl.EF,
-                             (const T*)pl.phiR, (const T*)pl.ER, self_c, comp,
-                             (T*)phi, (T*)efield, pl.partials, nb, energy,
-                             pl.stream);
+    rc = launch_combine<T>(N, (const T*)q, (const T*)pl.phiF, (const T*)pl.EF,
+                           (const T*)pl.phiR, (const T*)pl.ER, self_c, comp,
+                           (T*)phi, (T*)efield, pl.partials, nb, energy,
+                           pl.stream);
+    if (rc) return rc;
+    mask |= 32;
+    tmark(pl, 6);
+    if (pl.timing && pl.tcalls < kTimingMaxCalls) {
+        pl.tmask[pl.tcalls] = mask;
+        ++pl.tcalls;
+    }
+    return SE1P_OK;
 }
 
 template <typename T>
@@ -590,11 +627,52 @@ int se1p_plan_create(const se1p_params* params, long long n_max, void* stream,
     return SE1P_OK;
 }
 
+int se1p_timing_enable(se1p_plan* pl, int enable) {
+    if (!pl) return SE1P_ERR_ARG;
+    if (set_device(pl)) return SE1P_ERR_HIP;
+    if (enable && pl->tev.empty()) {
+        pl->tev.resize((size_t)kTimingMaxCalls * (SE1P_NSTAGE + 1));
+        for (auto& e : pl->tev) {
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                e = nullptr;
+                return SE1P_ERR_HIP;
+            }
+        }
+        pl->tmask.assign(kTimingMaxCalls, 0);
+    }
+    pl->timing = enable ? 1 : 0;
+    pl->tcalls = 0;
+    return SE1P_OK;
+}
+
+int se1p_timing_read(se1p_plan* pl, double* ms_sum, int* ncalls) {
+    if (!pl || !ms_sum) return SE1P_ERR_ARG;
+    for (int s = 0; s < SE1P_NSTAGE; ++s) ms_sum[s] = 0.0;
+    if (ncalls) *ncalls = pl->tcalls;
+    if (pl->tcalls == 0) return SE1P_OK;
+    if (set_device(pl)) return SE1P_ERR_HIP;
+    if (hipStreamSynchronize(pl->stream) != hipSuccess) return SE1P_ERR_HIP;
+    // stage s runs between boundaries: 0:[0,1] 1:[1,2] 2:[2,3] 3:[3,4]
+    // 4:[4,5] 5:[5,6]
+    for (int c = 0; c < pl->tcalls; ++c) {
+        const hipEvent_t* e = &pl->tev[(size_t)c * (SE1P_NSTAGE + 1)];
+        for (int s = 0; s < SE1P_NSTAGE; ++s) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e[s], e[s + 1]) != hipSuccess) return SE1P_ERR_HIP;
+            ms_sum[s] += ms;
+        }
+    }
+    return SE1P_OK;
+}
+
 int se1p_plan_destroy(se1p_plan* plan) {
     if (!plan) return SE1P_ERR_ARG;
     int rc = SE1P_OK;
     if (set_device(plan)) rc = SE1P_ERR_HIP;
     if (hipStreamSynchronize(plan->stream) != hipSuccess) rc = SE1P_ERR_HIP;
+    for (auto& e : plan->tev)
+        if (e) (void)hipEventDestroy(e);
     if (plan->base && hipFree(plan->base) != hipSuccess) rc = SE1P_ERR_HIP;
     delete plan;
     return rc;

@@ -95,7 +95,11 @@ EXPORTS = [
     "se1p_suggest_params", "se1p_plan_create", "se1p_plan_destroy",
     "se1p_plan_get_info", "se1p_set_stream", "se1p_eval", "se1p_spread",
     "se1p_kspace_solve", "se1p_gather", "se1p_error_string", "se1p_version",
+    "se1p_timing_enable", "se1p_timing_read",
 ]
+
+NSTAGE = 6
+STAGES = ["bin", "spread", "kspace", "gather", "realspace", "combine"]
 
 _LIB = None
 
@@ -133,6 +137,10 @@ def _lib():
     lib.se1p_kspace_solve.argtypes = [vp, vp, vp]
     lib.se1p_gather.restype = i
     lib.se1p_gather.argtypes = [vp, ll, vp, vp, vp, vp]
+    lib.se1p_timing_enable.restype = i
+    lib.se1p_timing_enable.argtypes = [vp, i]
+    lib.se1p_timing_read.restype = i
+    lib.se1p_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i)]
     _LIB = lib
     return lib
 
@@ -254,6 +262,16 @@ class Plan:
         self._sync_stream()
         _check(_lib().se1p_eval(self._h, x.shape[0], _ptr(x), _ptr(q), _ptr(phi),
                                 _ptr(E), _ptr(U), int(flags)), "se1p_eval")
+
+    def timing_enable(self, on=True):
+        _check(_lib().se1p_timing_enable(self._h, 1 if on else 0), "se1p_timing_enable")
+
+    def timing_read(self):
+        """(dict stage -> summed ms, number of calls); synchronises."""
+        arr = (ctypes.c_double * NSTAGE)()
+        n = ctypes.c_int()
+        _check(_lib().se1p_timing_read(self._h, arr, ctypes.byref(n)), "se1p_timing_read")
+        return {STAGES[k]: arr[k] for k in range(NSTAGE)}, n.value
 
     def grid_shape(self):
         i = self.info
