@@ -174,32 +174,65 @@ int check_params(const se1p_params& p) {
     return SE1P_OK;
 }
 
-// Gather block shape: lanes are particles, so aim for blocks holding close
-// to one wave of particles while keeping the union of the supports small.
+// Gather block shape: lanes are particles and every lane sweeps the union of
+// the supports of its chunk, so blocks should hold close to one wave of
+// particles while keeping the union small.  Expected cost per particle:
+//   E[chunks] * union / m, with Poisson counts of mean m = rho * cells,
+// penalised when the launch would not fill the chip.
+double poisson_chunks(double m) {
+    // E[ceil(k / 64)] for k ~ Poisson(m)
+    double pk = std::exp(-m), acc = 0.0;
+    const int kmax = (int)(m + 12.0 * std::sqrt(m + 1.0) + 80.0);
+    for (int k = 0; k <= kmax; ++k) {
+        if (k > 0) pk *= m / k;
+        acc += pk * ((k + 63) / 64);
+    }
+    return acc;
+}
+
 void choose_blocks(se1p_plan& pl) {
+    // Each chunk stages BZ + P - 1 grid planes of (BX + P - 1) x (BY + P - 1)
+    // values in LDS and every lane reads its own P x P window of each plane
+    // its z support covers.  Blocks keep BX * BY <= 32 with BY even and the
+    // LDS pitch == BY (mod 32), which spreads the lanes' window origins over
+    // distinct LDS banks.  Cost per particle: planes swept per chunk over the
+    // particles per chunk, with Poisson counts of mean m = rho * cells,
+    // penalised when the launch would not fill the chip.
     const double ncells = (double)pl.M1 * pl.M2 * pl.g.M3;
     const double rho = (double)std::max<long long>(pl.n_max, 1) / ncells;
     const int P = pl.g.P;
     double best = 1e300;
-    int bx = 1, by = 2, bz = 1;
-    const int bys[3] = {2, 4, 8};
+    int bx = 1, by = 2, bz = 1, ch = 1;
+    const int bys[4] = {2, 4, 8, 16};
     const int bzs[4] = {1, 2, 4, 8};
-    for (int iy = 0; iy < 3; ++iy)
-        for (int iz = 0; iz < 4; ++iz) {
-            const int BY = bys[iy], BZ = bzs[iz];
-            if (pl.g.M3 % BZ) continue;
-            for (int BX = 1; BX <= 16; ++BX) {
-                const double m = rho * BX * BY * BZ;   // expected particles
-                const double waves = std::max(1.0, std::ceil(m / 64.0 + 0.5));
-                const double per_wave_rows =
-                    (double)(BX + P - 1) * (BY + P - 1) * (BZ + P - 1);
-                // cost per particle ~ union points swept per lane / particles
-                const double cost = waves * per_wave_rows / std::max(m, 1e-3);
-                if (cost < best) { best = cost; bx = BX; by = BY; bz = BZ; }
+    for (int iz = 0; iz < 4; ++iz) {
+        const int BZ = bzs[iz];
+        if (pl.g.M3 % BZ) continue;
+        for (int iy = 0; iy < 4; ++iy) {
+            const int BY = bys[iy];
+            for (int BX = 1; BX * BY <= 32; ++BX) {
+                const double m = rho * BX * BY * BZ;
+                if (m > 64.0 && BX * BY * BZ > 2) continue;
+                const double nblocks = (double)((pl.M1 + BX - 1) / BX) *
+                                       ((pl.M2 + BY - 1) / BY) * (pl.g.M3 / BZ);
+                const double chunks = std::max(poisson_chunks(m), 1e-9);
+                const double planes = BZ + P - 1.0;
+                const double work = chunks * (planes * P * P * 2.0 +
+                                              planes * (BX + P - 1.0) * (BY + P - 1.0) / 16.0);
+                double cost = (work + 200.0) / std::max(m, 1e-6);
+                const double waves = nblocks * chunks;
+                if (waves < 2048.0) cost *= 2048.0 / std::max(waves, 1.0);
+                if (cost < best) {
+                    best = cost; bx = BX; by = BY; bz = BZ;
+                    ch = std::max(1, (int)std::ceil((m + 3.0 * std::sqrt(m) + 1.0) / 64.0));
+                }
             }
         }
+    }
     BinGeo& b = pl.bg;
-    b.BX = bx; b.BY = by; b.BZ = bz;
+    b.BX = bx; b.BY = by; b.BZ = bz; b.CH = ch;
+    const int Uy = by + P - 1;
+    b.ldy = Uy + (((by - Uy) % 32) + 32) % 32;   // >= Uy, == BY (mod 32), even
     b.nbx = (pl.M1 + bx - 1) / bx;
     b.nby = (pl.M2 + by - 1) / by;
     b.nbz = pl.g.M3 / bz;
@@ -355,7 +388,7 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     add(&pl.Hpart, (size_t)pl.KP * pl.pstride * pl.es);
     add(&pl.Fz, (size_t)pl.nslab * g.ncol * cs);
     add(&pl.G, (size_t)pl.slab_elems * cs);
-    add(&pl.Ht, (size_t)pl.pstride * pl.es);
+    add(&pl.Ht, (size_t)(pl.pstride + 64) * pl.es);   // rows are read in halves
     add(&pl.S0, (size_t)pl.n0[0] * pl.n0[1] * pl.es);
     add(&pl.tw, (size_t)pl.tw_elems * cs);
     add((void**)&pl.d_slabs, pl.slabs.size() * sizeof(SlabDesc));
@@ -770,17 +803,22 @@ int se1p_gather(se1p_plan* pl, long long N, const void* x, const void* grid,
     const double h3 = pl->g.h * pl->g.h * pl->g.h;
     const double sc = 4.0 * kPi * h3 * pl->cg;
     int rc;
-    // binning needs charges only for the sorted copies; reuse x as a dummy
-    // charge array is not possible (stride differs), so bin with phiF as q.
+    // The gather reads grid rows in halves and may touch one element past
+    // the last row; it runs on the plan's padded copy of the caller's grid.
+    if (hipMemcpyAsync(pl->Ht, grid, (size_t)pl->pstride * pl->es,
+                       hipMemcpyDeviceToDevice, pl->stream) != hipSuccess)
+        return SE1P_ERR_HIP;
+    // binning sorts charges along with positions; the gather does not use
+    // them, so the plan's scratch phiF stands in for q.
     if (pl->prec == SE1P_FP64) {
         if ((rc = run_bin<double>(*pl, N, x, pl->phiF))) return rc;
         DevParticles<double> blk = particles<double>(*pl, false);
-        return launch_gather<double>((const double*)grid, blk, N, pl->g, pl->bg, sc,
+        return launch_gather<double>((const double*)pl->Ht, blk, N, pl->g, pl->bg, sc,
                                      (double*)phi, (double*)efield, pl->stream);
     }
     if ((rc = run_bin<float>(*pl, N, x, pl->phiF))) return rc;
     DevParticles<float> blk = particles<float>(*pl, false);
-    return launch_gather<float>((const float*)grid, blk, N, pl->g, pl->bg, (float)sc,
+    return launch_gather<float>((const float*)pl->Ht, blk, N, pl->g, pl->bg, (float)sc,
                                 (float*)phi, (float*)efield, pl->stream);
 }
 

@@ -628,84 +628,171 @@ __global__ __launch_bounds__(256) void rowinv_kernel(
 // ------------------------------------------------------------------------
 // gather (step 6) and its gradient
 // ------------------------------------------------------------------------
-// One wave per block of BX x BY x BZ cells, lanes = particles (chunks of 64).
-// The union of the particles' supports is swept plane by plane (z) and row
-// by row (x); each row of UY = BY + P - 1 grid values along y is wave-uniform
-// and reaches the lanes through scalar loads.  The lane's own y weights are
-// kept in registers; x and z weights are recomputed per row.
-template <typename T, int P, int BY>
+// Lanes are particles: one wave takes a chunk of up to 64 particles of one
+// block of BX x BY x BZ cells (block blockIdx.x / CH, chunk slot
+// blockIdx.x % CH; further chunks of a block are strided by CH).  The grid
+// planes the chunk's supports touch are staged one at a time in LDS
+// (coalesced loads of the block's (BX + P - 1) x (BY + P - 1) footprint,
+// the next plane prefetched into registers while the current one is used);
+// each lane then reads its own P x P window of the plane from LDS.  y
+// weights live in registers, x weights follow the Gaussian-gridding
+// recurrence w(u+1) = w(u) r(u), r(u+1) = r(u) exp(-2 alpha h^2) in FP64
+// (FP32 evaluates exp directly), z weights are one exp per plane.
+constexpr int kGatherStage = 12; // staged plane values per lane in flight
+
+template <typename T, int P>
 __global__ __launch_bounds__(64) void gather_kernel(
     const T* __restrict__ Ht, const T* __restrict__ px,
     const T* __restrict__ py, const T* __restrict__ pz,
     const int* __restrict__ pcx, const int* __restrict__ pcy,
     const int* __restrict__ pcz, const int* __restrict__ perm,
-    const int* __restrict__ cstart, Geo g, BinGeo bg, T scale,
+    const int* __restrict__ cstart, Geo g, BinGeo bg, int CH, T scale,
     T* __restrict__ phi_out, T* __restrict__ E_out) {
-    constexpr int UY = P + BY - 1;
-    const int b = blockIdx.x;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    constexpr int HP = P / 2;         // the y window is swept in two halves
+    const int b = blockIdx.x / CH;
+    const int slot = blockIdx.x - b * CH;
     const int byk = b % bg.nby;
     const int tmp = b / bg.nby;
     const int bxk = tmp % bg.nbx;
     const int bzk = tmp / bg.nbx;
     const int s = cstart[(long long)b * bg.cpb];
     const int e = cstart[(long long)(b + 1) * bg.cpb];
-    if (s >= e) return;
-    const int X0u = bxk * bg.BX + 1;  // array index of the union start in x
-    const int Y0u = byk * BY + 1;
+    const int X0u = bxk * bg.BX + 1;  // array index of the footprint start
+    const int Y0u = byk * bg.BY + 1;
     const int Ux = bg.BX + P - 1;
-    const int Uz = bg.BZ + P - 1;
+    const int Uy = bg.BY + P - 1;
+    const int ldy = bg.ldy;           // LDS row pitch (see BinGeo)
     const int zl0 = bzk * bg.BZ - P / 2 + 1;  // z index of the union start
     const T h = (T)g.h, a = (T)g.alpha;
+    const T C2 = (T)exp(-2.0 * g.alpha * g.h * g.h);
+    const int lane = threadIdx.x;
+    const int plane_stride = Ux * ldy;
+    const int n16 = plane_stride * (int)sizeof(T) / 16;
 
-    for (int c0 = s; c0 < e; c0 += 64) {
-        const int p = c0 + (int)threadIdx.x;
+    for (int c0 = s + 64 * slot; c0 < e; c0 += 64 * CH) {
+        const int p = c0 + lane;
         const bool act = p < e;
         const int pp = act ? p : e - 1;
         const T x = px[pp], y = py[pp], z = pz[pp];
         const int ox = pcx[pp] - bxk * bg.BX;
-        const int oy = pcy[pp] - byk * BY;
+        const int oy = pcy[pp] - byk * bg.BY;
         const int oz = pcz[pp] - bzk * bg.BZ;
-
-        T wy[UY], ty[UY];
+        int ozmin = act ? oz : 1 << 20, ozmax = act ? oz : -(1 << 20);
 #pragma unroll
-        for (int u = 0; u < UY; ++u) {
-            const int dd = u - oy;
-            const T dy = y - (T)(Y0u + u - P / 2) * h;
-            const T w = (act && dd >= 0 && dd < P) ? dexp<T>(-a * dy * dy) : (T)0;
-            wy[u] = w;
-            ty[u] = dy * w;
+        for (int m = 32; m >= 1; m >>= 1) {
+            ozmin = min(ozmin, __shfl_xor(ozmin, m));
+            ozmax = max(ozmax, __shfl_xor(ozmax, m));
+        }
+        ozmin = __builtin_amdgcn_readfirstlane(ozmin);
+        ozmax = __builtin_amdgcn_readfirstlane(ozmax);
+        const int nplanes = ozmax - ozmin + P;
+
+        // distances from the particle to the first point of its window
+        const T dx0 = x - (T)(X0u + ox - P / 2) * h;
+        const T dy0 = y - (T)(Y0u + oy - P / 2) * h;
+        // Gaussian-gridding recurrence seeds (FP64): value and ratio at the
+        // window start and at the start of the second half in y
+        T wx0 = 0, rx0 = 0, wyA = 0, ryA = 0, wyB = 0, ryB = 0;
+        if constexpr (sizeof(T) == 8) {
+            wx0 = dexp<T>(-a * dx0 * dx0);
+            rx0 = dexp<T>(a * h * ((T)2 * dx0 - h));
+            wyA = dexp<T>(-a * dy0 * dy0);
+            ryA = dexp<T>(a * h * ((T)2 * dy0 - h));
+            const T dyB = dy0 - (T)HP * h;
+            wyB = dexp<T>(-a * dyB * dyB);
+            ryB = dexp<T>(a * h * ((T)2 * dyB - h));
         }
         T phi = 0, ex = 0, ey = 0, ez = 0;
-        for (int uz = 0; uz < Uz; ++uz) {
+
+        // Planes stream straight from global memory into LDS (16-byte
+        // global_load_lds chunks, 64 per instruction), one plane ahead of
+        // the plane being read.
+        auto stage = [&](int ip, T* buf) {
+            const T* src = Ht + (long long)imod(zl0 + ozmin + ip, g.M3) * g.ncol +
+                           (long long)X0u * g.Mt2 + Y0u;
+            constexpr int per16 = 16 / (int)sizeof(T);
+            for (int k = 0; k * 64 < n16; ++k) {
+                const int c = k * 64 + lane;
+                if (c < n16) {
+                    const int dd = c * per16;
+                    const int rr = dd / ldy;
+                    const int cc = dd - rr * ldy;
+                    __builtin_amdgcn_global_load_lds(
+                        (const void*)(src + (long long)rr * g.Mt2 + cc),
+                        (__attribute__((address_space(3))) void*)(buf + k * 64 * per16),
+                        16, 0, 0);
+                }
+            }
+        };
+        stage(0, lds);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        for (int ip = 0; ip < nplanes; ++ip) {
+            T* cur = lds + (ip & 1) * plane_stride;
+            T* nxt = lds + ((ip + 1) & 1) * plane_stride;
+            if (ip + 1 < nplanes) stage(ip + 1, nxt);
+            const int uz = ozmin + ip;
             const int dzi = uz - oz;
             const bool zin = act && dzi >= 0 && dzi < P;
-            if (!__any(zin)) continue;
             const T dz = z - (T)(zl0 + uz) * h;
             const T wzv = zin ? dexp<T>(-a * dz * dz) : (T)0;
             const T tz = dz * wzv;
-            const T* __restrict__ plane =
-                Ht + (long long)imod(zl0 + uz, g.M3) * g.ncol +
-                (long long)X0u * g.Mt2 + Y0u;
-            for (int ux = 0; ux < Ux; ++ux) {
-                const int dxi = ux - ox;
-                const bool xin = zin && dxi >= 0 && dxi < P;
-                if (!__any(xin)) continue;
-                const T dx = x - (T)(X0u + ux - P / 2) * h;
-                const T wx = xin ? dexp<T>(-a * dx * dx) : (T)0;
-                const T* __restrict__ row = plane + (long long)ux * g.Mt2;
-                T sy = 0, sty = 0;
+            if (__any(zin)) {
 #pragma unroll
-                for (int u = 0; u < UY; ++u) {
-                    const T hv = row[u];
-                    sy = fma(wy[u], hv, sy);
-                    sty = fma(ty[u], hv, sty);
+                for (int half = 0; half < 2; ++half) {
+                    // y weights of this half of the window (registers)
+                    T wy[HP], ty[HP];
+                    {
+                        T w = half ? wyB : wyA, rr = half ? ryB : ryA;
+#pragma unroll
+                        for (int u = 0; u < HP; ++u) {
+                            const T dy = dy0 - (T)(half * HP + u) * h;
+                            T wu;
+                            if constexpr (sizeof(T) == 8) {
+                                wu = w;
+                                w *= rr;
+                                rr *= C2;
+                            } else {
+                                wu = dexp<T>(-a * dy * dy);
+                            }
+                            wy[u] = wu;
+                            ty[u] = dy * wu;
+                        }
+                    }
+                    const T* base = cur + ox * ldy + oy + half * HP;
+                    T wrec = wx0, rrec = rx0;
+                    for (int dx = 0; dx < P; ++dx) {
+                        T wx;
+                        const T ddx = dx0 - (T)dx * h;
+                        if constexpr (sizeof(T) == 8) {
+                            wx = wrec;
+                            wrec *= rrec;
+                            rrec *= C2;
+                        } else {
+                            wx = dexp<T>(-a * ddx * ddx);
+                        }
+                        const T* row = base + dx * ldy;
+                        T hv[HP];
+#pragma unroll
+                        for (int u = 0; u < HP; ++u) hv[u] = row[u];
+                        T sy = 0, sty = 0;
+#pragma unroll
+                        for (int u = 0; u < HP; ++u) {
+                            sy = fma(wy[u], hv[u], sy);
+                            sty = fma(ty[u], hv[u], sty);
+                        }
+                        const T wxz = wx * wzv;
+                        phi = fma(wxz, sy, phi);
+                        ey = fma(wxz, sty, ey);
+                        ex = fma(ddx * wxz, sy, ex);
+                        ez = fma(wx * tz, sy, ez);
+                    }
                 }
-                const T wxz = wx * wzv;
-                phi = fma(wxz, sy, phi);
-                ey = fma(wxz, sty, ey);
-                ex = fma(dx * wxz, sy, ex);
-                ez = fma(wx * tz, sy, ez);
             }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
         }
         if (act) {
             const long long o = perm[p];
@@ -717,6 +804,7 @@ __global__ __launch_bounds__(64) void gather_kernel(
                 E_out[3 * o + 2] = f * ez;
             }
         }
+        __syncthreads();
     }
 }
 
@@ -993,28 +1081,19 @@ int launch_kspace(const T* Hin, int KP, long long pstride, T in_scale,
     return 0;
 }
 
-template <typename T, int P, int BY>
-static int gather_pb(const T* Ht, const DevParticles<T>& blk, const Geo& g,
-                     const BinGeo& bg, T scale, T* phi_out, T* E_out,
-                     hipStream_t s) {
-    const unsigned nb = (unsigned)(bg.nbx * bg.nby * bg.nbz);
-    hipLaunchKernelGGL((gather_kernel<T, P, BY>), dim3(nb), dim3(64), 0, s, Ht,
-                       blk.x, blk.y, blk.z, blk.cx, blk.cy, blk.cz, blk.perm,
-                       blk.start, g, bg, scale, phi_out, E_out);
-    SE1P_CHECK_LAUNCH();
-    return 0;
-}
-
 template <typename T, int P>
 static int gather_p(const T* Ht, const DevParticles<T>& blk, const Geo& g,
                     const BinGeo& bg, T scale, T* phi_out, T* E_out,
                     hipStream_t s) {
-    switch (bg.BY) {
-        case 2: return gather_pb<T, P, 2>(Ht, blk, g, bg, scale, phi_out, E_out, s);
-        case 4: return gather_pb<T, P, 4>(Ht, blk, g, bg, scale, phi_out, E_out, s);
-        case 8: return gather_pb<T, P, 8>(Ht, blk, g, bg, scale, phi_out, E_out, s);
-        default: return -8;
-    }
+    const unsigned nb = (unsigned)(bg.nbx * bg.nby * bg.nbz) * bg.CH;
+    const int Ux = bg.BX + P - 1, Uy = bg.BY + P - 1;
+    (void)Uy;
+    const size_t lds = 2 * (size_t)Ux * bg.ldy * sizeof(T);
+    hipLaunchKernelGGL((gather_kernel<T, P>), dim3(nb), dim3(64), lds, s, Ht,
+                       blk.x, blk.y, blk.z, blk.cx, blk.cy, blk.cz, blk.perm,
+                       blk.start, g, bg, bg.CH, scale, phi_out, E_out);
+    SE1P_CHECK_LAUNCH();
+    return 0;
 }
 
 template <typename T>
