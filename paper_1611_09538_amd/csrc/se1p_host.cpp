@@ -506,7 +506,8 @@ int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
     tmark(pl, 4);
     if ((comp & SE1P_REAL) && pl.prm.rc > 0.0) {
         DevParticles<T> lex = particles<T>(pl, true);
-        if ((rc = launch_realspace<T>(lex, N, pl.g, pl.prm.xi, pl.prm.rc,
+        DevParticles<T> blk = particles<T>(pl, false);
+        if ((rc = launch_realspace<T>(lex, blk, N, pl.g, pl.bg, pl.prm.xi, pl.prm.rc,
                                       (T*)pl.phiR, (T*)pl.ER, pl.stream)))
             return rc;
         mask |= 16;

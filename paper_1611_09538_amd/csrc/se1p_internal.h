@@ -101,9 +101,9 @@ int launch_gather(const T* Ht, const DevParticles<T>& blk, long long N,
                   T* E_out, hipStream_t s);
 
 template <typename T>
-int launch_realspace(const DevParticles<T>& lex, long long N, const Geo& g,
-                     double xi, double rc, T* phi_out, T* E_out,
-                     hipStream_t s);
+int launch_realspace(const DevParticles<T>& lex, const DevParticles<T>& blk,
+                     long long N, const Geo& g, const BinGeo& bg, double xi,
+                     double rc, T* phi_out, T* E_out, hipStream_t s);
 
 template <typename T>
 int launch_combine(long long N, const T* q_in, const T* phiF, const T* EF,

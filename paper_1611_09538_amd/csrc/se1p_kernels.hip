@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include "erfcx_poly.h"
 #include "se1p_internal.h"
 
 namespace se1p {
@@ -809,55 +810,178 @@ __global__ __launch_bounds__(64) void gather_kernel(
 }
 
 // ------------------------------------------------------------------------
-// real-space sum over the cell list (lex order, cells of size h)
+// real-space sum over the cell list (eq. ewald1p_real, eq. force_real)
 // ------------------------------------------------------------------------
+// One wave takes a chunk of up to 16 target particles of one block (the
+// gather's blocks); four lanes share a target and split its candidates.
+// Candidate sources are the cells within the cut-off of the chunk's cell
+// box, walked
+// as runs of the lex order (fixed z cell and x cell, a range of y cells
+// clipped to the cut-off sphere around the box; z wraps with the image
+// shift folded into the staged position).  Candidates are staged in LDS in
+// batches of 64.  A first pass sets, per lane, one bit per candidate of its
+// quarter within the cut-off; a second pass lets every lane pop its own
+// bits, so the erfc and exp run for in-range pairs only, with most lanes
+// busy.  The four partial sums of a target are added with lane shuffles.
+// erfc(xi r) / r and the radial field factor q (erfc(xi r)/r +
+// 2 xi/sqrt(pi) exp(-xi^2 r^2)) / r^2 of one pair.  FP64 shares the
+// exponential: erfc(x) = exp(-x^2) erfcx(x) with erfcx from the fitted
+// polynomial of erfcx_poly.h (relative error ~1e-14); FP32 uses the device
+// library's erfc and exp.
 template <typename T>
-__global__ __launch_bounds__(256) void realspace_kernel(
-    DevParticles<T> lx, long long N, Geo g, T xi, T rc, int R,
-    T* __restrict__ phi_out, T* __restrict__ E_out) {
-    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N) return;
-    const T x = lx.x[p], y = lx.y[p], z = lx.z[p];
-    const int cx = lx.cx[p], cy = lx.cy[p], cz = lx.cz[p];
+__device__ __forceinline__ void pair_terms(T r2, T xi, T xi2, T c_erf, T qn,
+                                           T& ec, T& f);
+template <>
+__device__ __forceinline__ void pair_terms<double>(double r2, double xi,
+                                                   double xi2, double c_erf,
+                                                   double qn, double& ec,
+                                                   double& f) {
+    const double rinv = rsqrt(r2);
+    const double r = r2 * rinv;
+    const double x = fmin(xi * r, kErfcxXmax);
+    const double e = exp(-xi2 * r2);
+    const double den = 1.0 + kErfcxA * x;
+    double t = __builtin_amdgcn_rcp(den);
+    t = t * (2.0 - den * t);
+    t = t * (2.0 - den * t);
+    const double cu = 2.0 / (1.0 - kErfcxTmin);
+    const double u = fma(t, cu, -1.0 - kErfcxTmin * cu);
+    double pv = kErfcxC[kErfcxDeg];
+#pragma unroll
+    for (int k = kErfcxDeg - 1; k >= 0; --k) pv = fma(pv, u, kErfcxC[k]);
+    ec = e * (t * pv) * rinv;
+    f = qn * (ec + c_erf * e) * (rinv * rinv);
+}
+template <>
+__device__ __forceinline__ void pair_terms<float>(float r2, float xi,
+                                                  float xi2, float c_erf,
+                                                  float qn, float& ec,
+                                                  float& f) {
+    const float rinv = rsqrtf(r2);
+    const float r = r2 * rinv;
+    ec = erfcf(xi * r) * rinv;
+    f = qn * (ec + c_erf * __expf(-xi2 * r2)) * (rinv * rinv);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void realspace_kernel(
+    DevParticles<T> blk, DevParticles<T> lx, Geo g, BinGeo bg, int CH, T xi,
+    T rc, int R, T* __restrict__ phi_out, T* __restrict__ E_out) {
+    __shared__ T cx_[64], cy_[64], cz_[64], cq_[64];
+    const int b = blockIdx.x / CH;
+    const int slot = blockIdx.x - b * CH;
+    const int s0 = blk.start[(long long)b * bg.cpb];
+    const int e0 = blk.start[(long long)(b + 1) * bg.cpb];
+    const int lane = threadIdx.x;
+    const int tq = lane >> 2;         // target of this lane within the chunk
+    const int kq = lane & 3;          // quarter of each candidate batch
     const T rc2 = rc * rc;
     const T c_erf = (T)1.1283791670955125738961589031215 * xi;  // 2 xi / sqrt(pi)
     const T xi2 = xi * xi;
     const T L3 = (T)g.L3;
-    T phi = 0, ex = 0, ey = 0, ez = 0;
-    const int ylo = max(0, cy - R), yhi = min(g.M2 - 1, cy + R);
-    const int xlo = max(0, cx - R), xhi = min(g.M1 - 1, cx + R);
-    for (int dzc = -R; dzc <= R; ++dzc) {
-        const int czu = cz + dzc;
-        const int czw = imod(czu, g.M3);
-        const int img = (czu - czw) / g.M3;
-        const T shift = (T)img * L3;
-        for (int cxn = xlo; cxn <= xhi; ++cxn) {
-            const long long cb = ((long long)czw * g.M1 + cxn) * g.M2;
-            const int s = lx.start[cb + ylo];
-            const int e = lx.start[cb + yhi + 1];
-            for (int n = s; n < e; ++n) {
-                if (n == p && img == 0) continue;
-                const T dx = x - lx.x[n];
-                const T dy = y - lx.y[n];
-                const T dz = z - (lx.z[n] + shift);
+    const double rcell2 = (double)rc * (double)rc / (g.h * g.h);
+
+    // chunks of 16 targets; four lanes share a target and split its
+    // candidates
+    for (int c0 = s0 + 16 * slot; c0 < e0; c0 += 16 * CH) {
+        const int p = c0 + tq;
+        const bool act = p < e0;
+        const int pp = act ? p : e0 - 1;
+        const T xt = blk.x[pp], yt = blk.y[pp], zt = blk.z[pp];
+        // cell box of the chunk's targets
+        int mnx = act ? blk.cx[pp] : 1 << 20, mxx = act ? blk.cx[pp] : -(1 << 20);
+        int mny = act ? blk.cy[pp] : 1 << 20, mxy = act ? blk.cy[pp] : -(1 << 20);
+        int mnz = act ? blk.cz[pp] : 1 << 20, mxz = act ? blk.cz[pp] : -(1 << 20);
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            mnx = min(mnx, __shfl_xor(mnx, m)); mxx = max(mxx, __shfl_xor(mxx, m));
+            mny = min(mny, __shfl_xor(mny, m)); mxy = max(mxy, __shfl_xor(mxy, m));
+            mnz = min(mnz, __shfl_xor(mnz, m)); mxz = max(mxz, __shfl_xor(mxz, m));
+        }
+        const int bx0 = __builtin_amdgcn_readfirstlane(mnx), bx1 = __builtin_amdgcn_readfirstlane(mxx);
+        const int by0 = __builtin_amdgcn_readfirstlane(mny), by1 = __builtin_amdgcn_readfirstlane(mxy);
+        const int bz0 = __builtin_amdgcn_readfirstlane(mnz), bz1 = __builtin_amdgcn_readfirstlane(mxz);
+        T phi = 0, ex = 0, ey = 0, ez = 0;
+        int fill = 0;
+
+        auto process = [&](int n) {
+            __syncthreads();
+            // pass 1: one bit per in-range candidate j = kq + 4 i
+            unsigned int mask = 0u;
+            for (int i = 0; 4 * i < n; ++i) {
+                const int j = kq + 4 * i;
+                const T dx = xt - cx_[j], dy = yt - cy_[j], dz = zt - cz_[j];
                 const T r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 > rc2) continue;
-                const T r = sqrt(r2);
-                const T qn = lx.q[n];
-                const T ec = erfc(xi * r) / r;
-                phi += qn * ec;
-                const T f = qn * (ec + c_erf * exp(-xi2 * r2)) / r2;
-                ex += f * dx;
-                ey += f * dy;
-                ez += f * dz;
+                const bool in = act && (j < n) && (r2 <= rc2) && (r2 > (T)0);
+                mask |= (unsigned int)in << i;
+            }
+            // pass 2: every lane works through its own in-range candidates
+            while (__any(mask != 0u)) {
+                if (mask != 0u) {
+                    const int j = kq + 4 * __builtin_ctz(mask);
+                    mask &= mask - 1u;
+                    const T dx = xt - cx_[j], dy = yt - cy_[j], dz = zt - cz_[j];
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    const T qn = cq_[j];
+                    T ec, f;
+                    pair_terms<T>(r2, xi, xi2, c_erf, qn, ec, f);
+                    phi += qn * ec;
+                    ex += f * dx;
+                    ey += f * dy;
+                    ez += f * dz;
+                }
+            }
+            __syncthreads();
+        };
+
+        for (int czu = bz0 - R; czu <= bz1 + R; ++czu) {
+            const int gz = max(0, max(bz0 - czu, czu - bz1) - 1);
+            const int czw = imod(czu, g.M3);
+            const T shift = (T)((czu - czw) / g.M3) * L3;
+            for (int cxn = max(0, bx0 - R); cxn <= min(g.M1 - 1, bx1 + R); ++cxn) {
+                const int gx = max(0, max(bx0 - cxn, cxn - bx1) - 1);
+                const double rem = rcell2 - (double)gz * gz - (double)gx * gx;
+                if (rem < 0.0) continue;
+                const int gy = (int)sqrt(rem) + 1;
+                const int ylo = max(0, by0 - gy), yhi = min(g.M2 - 1, by1 + gy);
+                const long long cb = ((long long)czw * g.M1 + cxn) * g.M2;
+                int s = lx.start[cb + ylo];
+                const int e = lx.start[cb + yhi + 1];
+                while (s < e) {
+                    const int take = min(e - s, 64 - fill);
+                    if (lane < take) {
+                        const int n = s + lane;
+                        cx_[fill + lane] = lx.x[n];
+                        cy_[fill + lane] = lx.y[n];
+                        cz_[fill + lane] = lx.z[n] + shift;
+                        cq_[fill + lane] = lx.q[n];
+                    }
+                    fill += take;
+                    s += take;
+                    if (fill == 64) {
+                        process(64);
+                        fill = 0;
+                    }
+                }
             }
         }
+        if (fill > 0) process(fill);
+        // sum the four lanes of each target
+#pragma unroll
+        for (int m = 1; m <= 2; m <<= 1) {
+            phi += __shfl_xor(phi, m);
+            ex += __shfl_xor(ex, m);
+            ey += __shfl_xor(ey, m);
+            ez += __shfl_xor(ez, m);
+        }
+        if (act && kq == 0) {
+            const long long o = blk.perm[p];
+            phi_out[o] = phi;
+            E_out[3 * o] = ex;
+            E_out[3 * o + 1] = ey;
+            E_out[3 * o + 2] = ez;
+        }
     }
-    const long long o = lx.perm[p];
-    phi_out[o] = phi;
-    E_out[3 * o] = ex;
-    E_out[3 * o + 1] = ey;
-    E_out[3 * o + 2] = ez;
 }
 
 // ------------------------------------------------------------------------
@@ -1111,12 +1235,15 @@ int launch_gather(const T* Ht, const DevParticles<T>& blk, long long N,
 }
 
 template <typename T>
-int launch_realspace(const DevParticles<T>& lex, long long N, const Geo& g,
-                     double xi, double rc, T* phi_out, T* E_out,
-                     hipStream_t s) {
+int launch_realspace(const DevParticles<T>& lex, const DevParticles<T>& blk,
+                     long long N, const Geo& g, const BinGeo& bg, double xi,
+                     double rc, T* phi_out, T* E_out, hipStream_t s) {
+    (void)N;
     const int R = (int)ceil(rc / g.h);
-    hipLaunchKernelGGL(realspace_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0, s,
-                       lex, N, g, (T)xi, (T)rc, R, phi_out, E_out);
+    const int CHr = 4 * bg.CH;   // chunks of 16 targets
+    const unsigned nb = (unsigned)(bg.nbx * bg.nby * bg.nbz) * CHr;
+    hipLaunchKernelGGL(realspace_kernel<T>, dim3(nb), dim3(64), 0, s, blk, lex,
+                       g, bg, CHr, (T)xi, (T)rc, R, phi_out, E_out);
     SE1P_CHECK_LAUNCH();
     return 0;
 }
@@ -1165,9 +1292,10 @@ int launch_check(const T* x, const T* q, long long N, double L1, double L2,
     template int launch_gather<T>(const T*, const DevParticles<T>&, long long, \
                                   const Geo&, const BinGeo&, T, T*, T*,         \
                                   hipStream_t);                                 \
-    template int launch_realspace<T>(const DevParticles<T>&, long long,        \
-                                     const Geo&, double, double, T*, T*,        \
-                                     hipStream_t);                              \
+    template int launch_realspace<T>(const DevParticles<T>&,                   \
+                                     const DevParticles<T>&, long long,         \
+                                     const Geo&, const BinGeo&, double, double, \
+                                     T*, T*, hipStream_t);                      \
     template int launch_combine<T>(long long, const T*, const T*, const T*,    \
                                    const T*, const T*, double, unsigned, T*,    \
                                    T*, double*, int, double*, hipStream_t);     \
