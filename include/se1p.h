@@ -145,8 +145,10 @@ typedef struct se1p_plan se1p_plan;
  *   - rc from the real-space estimate (eq. rc);
  *   - P from eq. approximation_error_oneterm when P_in <= 0 (rounded up to
  *     even), else P_in;
- *   - s_l from eq. choose_sl generalised to a non-square box
- *     (exp(-2 pi s_l L~ / L3) < tol) and n_l from eq. choose_nl (M3 ~ 10 n_l)
+ *   - s_l from eq. choose_sl generalised to any box: the padded period
+ *     leaves (s_l - 1) L~ between the support and its nearest image, and
+ *     exp(-2 pi (s_l - 1) L~ / L3) < tol, with L~ the smaller extended side;
+ *     n_l from eq. choose_nl (M3 ~ 10 n_l)
  *     when n_l_in < 0, else n_l_in;
  *   - s0 = 1 + sqrt(2) (minimum of section 3.4).
  * precision: SE1P_FP64 or SE1P_FP32.  Writes *out; returns an error code.
@@ -237,6 +239,100 @@ int se1p_gather(se1p_plan* plan, long long N, const void* x,
 #define SE1P_NSTAGE 6
 int se1p_timing_enable(se1p_plan* plan, int enable);
 int se1p_timing_read(se1p_plan* plan, double* ms_sum, int* ncalls);
+
+/* ---- batches: many independent systems in one set of launches ----------
+ *
+ * A batch evaluates nsys independent neutral systems, each with its own box,
+ * particle count and method parameters (all systems share the precision and
+ * the support P), with one launch per stage for all of them: particle-wise
+ * stages run over the packed particles, grid-shaped stages (gridding, the
+ * transforms of Algorithms 2-3 with scaling, gathering, real space, totals)
+ * are persistent kernels pulling (system, tile) work items, largest first,
+ * from a queue.  Particles of system s occupy rows [p_s, p_s + counts[s]) of
+ * the packed arrays, p_s = sum of the earlier counts.
+ */
+typedef struct se1p_batch se1p_batch;
+
+/* Per-stage cost coefficients of the autotuner (nanoseconds per unit). */
+typedef struct se1p_cost_model {
+    double pair_ns;      /* real space, per particle pair within rc */
+    double grid_ns;      /* gridding + gathering, per particle support point (P^3) */
+    double fft_ns;       /* transforms, per point x log2(length) of every 1D FFT */
+    double particle_ns;  /* binning, weights and totals, per particle */
+    double system_ns;    /* fixed cost per system (tables, queue items) */
+} se1p_cost_model;
+
+/*
+ * se1p_calibrate -- measures the cost model on the current device: builds a
+ * probe plan (20000 neutral +-1 charges in a unit box at tol, with the given
+ * precision and P), times its stages over a few evaluations with HIP events
+ * and fits one coefficient per stage.  Synchronises; allocates and frees
+ * the probe's workspace.
+ */
+int se1p_calibrate(double tol, int precision, int P, void* stream,
+                   se1p_cost_model* out);
+
+/*
+ * se1p_autotune -- host only.  For every system s (box boxes[3s..3s+2],
+ * counts[s] particles, Q[s] = sum q^2 or NULL for counts[s], i.e. unit
+ * charges) picks the parameters meeting the RMS error tol (section 4.3
+ * recipe as in se1p_suggest_params) with the smallest predicted cost: M3
+ * runs over FFT-friendly even sizes >= P; each fixes xi by the Fourier
+ * estimate, rc by the real-space estimate and the slab upsampling; the cost
+ * adds the model's terms for the expected real-space pairs, the N P^3
+ * gridding work and the transform work of the planned grid.  model NULL
+ * uses built-in MI355X coefficients.  Tile shapes (gather blocks, gridding
+ * chunks) are then chosen per system by the planner's own cost models.
+ * Writes out[0..nsys-1].
+ */
+int se1p_autotune(double tol, int nsys, const double* boxes,
+                  const long long* counts, const double* Q, int precision,
+                  int P, const se1p_cost_model* model, se1p_params* out);
+
+/*
+ * se1p_batch_create -- plans every system (params[s], counts[s] >= 1
+ * particles) and allocates one workspace for the batch on the current
+ * device.  All params must share precision and P.  stream as for plans.
+ */
+int se1p_batch_create(int nsys, const se1p_params* params,
+                      const long long* counts, void* stream,
+                      se1p_batch** out);
+int se1p_batch_destroy(se1p_batch* batch);
+
+/*
+ * se1p_batch_eval -- evaluates every system.
+ *   x, q, phi, efield  packed device arrays as in se1p_eval over all
+ *                      particles (phi / efield may be NULL).
+ *   energy             device, nsys doubles (U of each system), or NULL.
+ *   flags              SE1P_KSPACE | SE1P_REAL | SE1P_SELF, optionally
+ *                      SE1P_BATCH_EAGER.
+ * Unless SE1P_BATCH_EAGER, the whole sequence is captured once into a HIP
+ * graph (on the batch's own capture stream) and replayed with one
+ * hipGraphLaunch on the batch's stream; the graph is captured again when
+ * the buffer addresses or flags differ from the previous call.  Inputs are
+ * not validated on the device.
+ */
+#define SE1P_BATCH_EAGER 64u
+int se1p_batch_eval(se1p_batch* batch, const void* x, const void* q,
+                    void* phi, void* efield, double* energy, unsigned flags);
+
+typedef struct se1p_batch_info {
+    int       nsys;
+    int       precision;
+    int       P;
+    long long n_total;          /* packed particles */
+    size_t    workspace_bytes;
+    int       items[10];        /* queue items per stage: spread, z FFT, row
+                                   FFT, column pass, inverse rows, inverse z,
+                                   gather, real space, totals, (unused) */
+    int       grid[10];         /* persistent blocks launched per stage */
+    int       graph_captures;   /* graphs captured so far */
+} se1p_batch_info;
+int se1p_batch_get_info(const se1p_batch* batch, se1p_batch_info* info);
+
+/* Parameters and derived geometry of system s of a batch. */
+int se1p_batch_system_info(const se1p_batch* batch, int s, se1p_params* params,
+                           se1p_plan_info* info);
 
 /* Human-readable text for an error code (static storage). */
 const char* se1p_error_string(int code);

@@ -11,18 +11,12 @@
 #include <new>
 #include <vector>
 
-#include "../../include/se1p.h"
-#include "se1p_internal.h"
-
-namespace se1p {
-size_t scan_temp_bytes(long long n);
-}
+#include "se1p_plan.h"
 
 using namespace se1p;
 
 namespace {
 
-constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kShapeC = 0.95;  // c in eq. comp_eta
 
 // smallest integer >= n whose only prime factors are 2, 3, 5
@@ -90,57 +84,6 @@ struct Buf {
 
 }  // namespace
 
-struct se1p_plan {
-    se1p_params prm;
-    int prec = 0;           // SE1P_FP64 / SE1P_FP32
-    size_t es = 8;          // element size
-    long long n_max = 0;
-    int device = 0;
-    hipStream_t stream = nullptr;
-
-    Geo g{};
-    BinGeo bg{};
-    double cg = 0.0;        // (2 xi^2 / (pi eta))^{3/2}
-    double R = 0.0;
-    int M1 = 0, M2 = 0;
-    int n0[2] = {0, 0}, nl[2] = {0, 0};
-    int nslab = 0;
-    int CZ = 0, KP = 0;
-    std::vector<SlabDesc> slabs;
-    FftDesc dz{};
-    long long tw_elems = 0;
-    long long slab_elems = 0;
-
-    // device memory (single allocation, carved)
-    void* base = nullptr;
-    size_t ws_bytes = 0;
-    int *key_lex = nullptr, *key_blk = nullptr, *slot_lex = nullptr, *slot_blk = nullptr;
-    int *cnt_lex = nullptr, *cnt_blk = nullptr;
-    int *lex_i[5] = {}, *blk_i[5] = {};   // cx, cy, cz, perm, start
-    void *lex_f[4] = {}, *blk_f[4] = {};  // x, y, z, q
-    void* scan_tmp = nullptr;
-    size_t scan_bytes = 0;
-    void *wz = nullptr, *wxp = nullptr, *wyq = nullptr;
-    void* Hpart = nullptr;
-    long long pstride = 0;
-    void* Fz = nullptr;
-    void* G = nullptr;
-    void* Ht = nullptr;
-    void* S0 = nullptr;
-    void* tw = nullptr;
-    SlabDesc* d_slabs = nullptr;
-    void *phiF = nullptr, *EF = nullptr, *phiR = nullptr, *ER = nullptr;
-    double* partials = nullptr;
-    int nblk_comb = 0;
-    int* flag = nullptr;
-    double* qsum = nullptr;
-
-    // stage timing: events[call][boundary], boundaries 0..SE1P_NSTAGE
-    int timing = 0;
-    int tcalls = 0;
-    std::vector<hipEvent_t> tev;
-    std::vector<unsigned char> tmask;   // stages run per call
-};
 
 namespace {
 constexpr int kTimingMaxCalls = 4096;
@@ -202,7 +145,8 @@ void choose_blocks(se1p_plan& pl) {
     const double rho = (double)std::max<long long>(pl.n_max, 1) / ncells;
     const int P = pl.g.P;
     double best = 1e300;
-    int bx = 1, by = 2, bz = 1, ch = 1;
+    const int bymin = std::max(2, 16 / (int)pl.es);   // whole 16-byte chunks
+    int bx = 1, by = bymin, bz = 1, ch = 1;
     const int bys[4] = {2, 4, 8, 16};
     const int bzs[4] = {1, 2, 4, 8};
     for (int iz = 0; iz < 4; ++iz) {
@@ -210,9 +154,12 @@ void choose_blocks(se1p_plan& pl) {
         if (pl.g.M3 % BZ) continue;
         for (int iy = 0; iy < 4; ++iy) {
             const int BY = bys[iy];
+            // planes are staged in 16-byte chunks: with ldy == BY (mod 32)
+            // the pitch holds whole chunks only if BY does
+            if ((BY * (int)pl.es) % 16) continue;
             for (int BX = 1; BX * BY <= 32; ++BX) {
                 const double m = rho * BX * BY * BZ;
-                if (m > 64.0 && BX * BY * BZ > 2) continue;
+                if (m > 64.0 && BX * BY * BZ > bymin) continue;
                 const double nblocks = (double)((pl.M1 + BX - 1) / BX) *
                                        ((pl.M2 + BY - 1) / BY) * (pl.g.M3 / BZ);
                 const double chunks = std::max(poisson_chunks(m), 1e-9);
@@ -232,7 +179,7 @@ void choose_blocks(se1p_plan& pl) {
     BinGeo& b = pl.bg;
     b.BX = bx; b.BY = by; b.BZ = bz; b.CH = ch;
     const int Uy = by + P - 1;
-    b.ldy = Uy + (((by - Uy) % 32) + 32) % 32;   // >= Uy, == BY (mod 32), even
+    b.ldy = Uy + (((by - Uy) % 32) + 32) % 32;   // >= Uy, == BY (mod 32)
     b.nbx = (pl.M1 + bx - 1) / bx;
     b.nby = (pl.M2 + by - 1) / by;
     b.nbz = pl.g.M3 / bz;
@@ -274,11 +221,16 @@ DevParticles<T> particles(const se1p_plan& pl, bool lex) {
     void* const* f = lex ? pl.lex_f : pl.blk_f;
     int* const* i = lex ? pl.lex_i : pl.blk_i;
     d.x = (T*)f[0]; d.y = (T*)f[1]; d.z = (T*)f[2]; d.q = (T*)f[3];
+    d.tx = (T*)f[4]; d.ty = (T*)f[5]; d.tz = (T*)f[6];
     d.cx = i[0]; d.cy = i[1]; d.cz = i[2]; d.perm = i[3]; d.start = i[4];
     return d;
 }
 
-int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
+}  // namespace
+
+int se1p::plan_check_params(const se1p_params& p) { return check_params(p); }
+
+int se1p::plan_geometry(se1p_plan& pl, const se1p_params& p, long long n_max) {
     pl.prm = p;
     pl.prec = p.precision;
     pl.es = (p.precision == SE1P_FP64) ? 8 : 4;
@@ -300,6 +252,9 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     g.M1 = pl.M1;
     g.M2 = pl.M2;
     choose_blocks(pl);
+    // the gather stages planes of Ux x ldy values in 16-byte chunks that
+    // must not straddle LDS rows
+    if ((pl.bg.ldy * pl.es) % 16 != 0) return SE1P_ERR_UNSUPPORTED;
     // Extended grid: M + P plus room for whole gather blocks, FFT-friendly.
     g.Mt1 = nice_size(std::max(pl.bg.nbx * pl.bg.BX + p.P, pl.M1 + p.P + p.pad_free));
     g.Mt2 = nice_size(std::max(pl.bg.nby * pl.bg.BY + p.P, pl.M2 + p.P + p.pad_free));
@@ -323,7 +278,8 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     // slabs n3 = 0 .. M3/2 (eq. upsamplings)
     pl.nslab = p.M3 / 2 + 1;
     pl.slabs.resize(pl.nslab);
-    std::map<int, int> twoff;   // length -> offset
+    std::map<int, int>& twoff = pl.twoff;   // length -> offset
+    twoff.clear();
     long long twn = 0;
     auto tw_of = [&](int n) {
         auto it = twoff.find(n);
@@ -362,6 +318,46 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     const size_t lds_r = 2 * 4 * (size_t)n2max * cs;
     const size_t lds_c = 2 * 4 * (size_t)(n1max + 1) * cs;
     if (std::max({lds_z, lds_r, lds_c}) > 160 * 1024) return SE1P_ERR_UNSUPPORTED;
+    return SE1P_OK;
+}
+
+void se1p::plan_tables(const se1p_plan& pl, std::vector<double>& twd,
+                       std::vector<double>& s0) {
+    const Geo& g = pl.g;
+    twd.assign(2 * pl.tw_elems, 0.0);
+    for (auto& kv : pl.twoff) {
+        const int n = kv.first, o = kv.second;
+        for (int k = 0; k < n; ++k) {
+            const double ang = -2.0 * kPi * (double)k / (double)n;
+            twd[2 * (o + k)] = std::cos(ang);
+            twd[2 * (o + k) + 1] = std::sin(ang);
+        }
+    }
+    const int a0 = pl.n0[0], b0 = pl.n0[1];
+    s0.assign(a0 * (size_t)b0, 0.0);
+    const SlabDesc& z0 = pl.slabs[0];
+    for (int kx = 0; kx < a0; ++kx) {
+        const int fx = (kx <= a0 / 2) ? kx : kx - a0;
+        const double k1 = 2.0 * kPi * fx / (a0 * g.h);
+        for (int ky = 0; ky < b0; ++ky) {
+            const int fy = (ky <= b0 / 2) ? ky : ky - b0;
+            const double k2 = 2.0 * kPi * fy / (b0 * g.h);
+            const double kap2 = k1 * k1 + k2 * k2;
+            double v = z0.pref * std::exp(-(1.0 - g.eta) * kap2 / (4.0 * pl.prm.xi * pl.prm.xi)) *
+                       G_R(std::sqrt(kap2), pl.R);
+            if (kx == 0 && ky == 0) v = 0.0;   // (kappa, k3) = (0, 0)
+            s0[(size_t)kx * b0 + ky] = v;
+        }
+    }
+}
+
+namespace {
+
+int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
+    int rc0 = plan_geometry(pl, p, n_max);
+    if (rc0) return rc0;
+    const Geo& g = pl.g;
+    const size_t cs = 2 * pl.es;
 
     // ---- workspace layout ----
     const long long N = std::max<long long>(n_max, 1);
@@ -376,7 +372,7 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     for (int k = 0; k < 4; ++k) { add((void**)&pl.lex_i[k], N * 4); add((void**)&pl.blk_i[k], N * 4); }
     add((void**)&pl.lex_i[4], (pl.bg.ncell_lex + 1) * 4);
     add((void**)&pl.blk_i[4], (pl.bg.ncell_blk + 1) * 4);
-    for (int k = 0; k < 4; ++k) { add(&pl.lex_f[k], N * pl.es); add(&pl.blk_f[k], N * pl.es); }
+    for (int k = 0; k < 7; ++k) { add(&pl.lex_f[k], N * pl.es); add(&pl.blk_f[k], N * pl.es); }
     pl.scan_bytes = std::max(scan_temp_bytes(pl.bg.ncell_lex + 1),
                              scan_temp_bytes(pl.bg.ncell_blk + 1)) + 256;
     add(&pl.scan_tmp, pl.scan_bytes);
@@ -412,31 +408,8 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     for (auto& r : req) { *r.first = cur; cur += r.second; }
 
     // ---- tables: twiddles, slab descriptors, FP64 scaling of slab 0 ----
-    std::vector<double> twd(2 * pl.tw_elems);
-    for (auto& kv : twoff) {
-        const int n = kv.first, o = kv.second;
-        for (int k = 0; k < n; ++k) {
-            const double ang = -2.0 * kPi * (double)k / (double)n;
-            twd[2 * (o + k)] = std::cos(ang);
-            twd[2 * (o + k) + 1] = std::sin(ang);
-        }
-    }
-    const int a0 = pl.n0[0], b0 = pl.n0[1];
-    std::vector<double> s0(a0 * (size_t)b0);
-    const SlabDesc& z0 = pl.slabs[0];
-    for (int kx = 0; kx < a0; ++kx) {
-        const int fx = (kx <= a0 / 2) ? kx : kx - a0;
-        const double k1 = 2.0 * kPi * fx / (a0 * g.h);
-        for (int ky = 0; ky < b0; ++ky) {
-            const int fy = (ky <= b0 / 2) ? ky : ky - b0;
-            const double k2 = 2.0 * kPi * fy / (b0 * g.h);
-            const double kap2 = k1 * k1 + k2 * k2;
-            double v = z0.pref * std::exp(-(1.0 - g.eta) * kap2 / (4.0 * p.xi * p.xi)) *
-                       G_R(std::sqrt(kap2), pl.R);
-            if (kx == 0 && ky == 0) v = 0.0;   // (kappa, k3) = (0, 0)
-            s0[(size_t)kx * b0 + ky] = v;
-        }
-    }
+    std::vector<double> twd, s0;
+    plan_tables(pl, twd, s0);
     hipError_t e = hipSuccess;
     if (pl.prec == SE1P_FP64) {
         e = hipMemcpy(pl.tw, twd.data(), twd.size() * 8, hipMemcpyHostToDevice);
@@ -630,10 +603,13 @@ int se1p_suggest_params(double tol, const double box[3], long long N, double Q,
         p.P = std::min(std::max(P, 4), kMaxP);
     }
     if (p.P > p.M3) p.P = p.M3 - (p.M3 & 1);
-    // eq. choose_sl generalised: exp(-2 pi s_l Lt / L3) < tol
+    // eq. choose_sl generalised to any box: the first k3 mode's kernel
+    // decays like exp(-2 pi d / L3) with the distance d to the nearest
+    // periodic image of the support in the padded period, d = (s_l - 1) Lt,
+    // so exp(-2 pi (s_l - 1) Lt / L3) < tol
     const double h = L / p.M3;
     const double Lt = std::min(std::ceil(box[0] / h - 1e-9), std::ceil(box[1] / h - 1e-9)) * h + p.P * h;
-    p.s_l = std::max(1.0, std::log(1.0 / tol) * L / (2.0 * kPi * Lt));
+    p.s_l = 1.0 + std::log(1.0 / tol) * L / (2.0 * kPi * Lt);
     // eq. choose_nl: M ~ 10 n_l
     p.n_l = (n_l_in >= 0) ? n_l_in : std::max(1, (int)std::lround(p.M3 / 10.0));
     p.s0 = 1.0 + std::sqrt(2.0);

@@ -67,6 +67,10 @@ template <typename T> using cplx = typename cplx_t<T>::type;
 template <typename T>
 struct DevParticles {        // sorted copies of the particles in one order
     T* x; T* y; T* z; T* q;  // z wrapped into [0, L3)
+    T* tx; T* ty; T* tz;     // offsets inside the cell in units of h:
+                             // x / h - cx, computed in FP64, so that the
+                             // Gaussian weights do not lose the digits of
+                             // x - grid point to the size of x
     int* cx; int* cy; int* cz;
     int* perm;               // sorted position -> input index
     int* start;              // cell starts, size ncell + 1
@@ -116,5 +120,77 @@ int launch_check(const T* x, const T* q, long long N, double L1, double L2,
                  int* flag, double* qsum, hipStream_t s);
 
 int launch_fill_int(int* p, long long n, int v, hipStream_t s);
+
+// ---- batches: many independent systems per launch --------------------------
+// Particles of all systems are packed system after system; the cell arrays
+// of all systems are packed the same way, so one scan over the packed counts
+// yields global cell starts whose values index the packed particle arrays.
+// Grid-shaped stages run as work queues over (system, tile) items.
+template <typename T>
+struct SysDesc {
+    Geo g;
+    BinGeo bg;
+    FftDesc dz;
+    const SlabDesc* slabs;      // device, offsets relative to G
+    T* Hpart;                   // KP partial grids, pstride apart
+    cplx<T>* Fz;
+    cplx<T>* G;
+    T* Ht;
+    const T* S0;
+    long long pstride;
+    long long p0, n;            // packed particle range
+    long long cl0, cb0;         // first lex / block cell in the packed cell arrays
+    long long e0;               // first energy partial of this system
+    int CZ, KP, R, nslab;
+    int ncomb;                  // energy partial blocks (256 particles each)
+    int rs;                     // real-space sum enabled (rc > 0)
+    double xi, rc, self_c;
+};
+
+// One queue item: system and up to three tile coordinates.
+struct Item {
+    int sys, a, b, c;
+};
+
+// Stages with work queues, in launch order.
+enum BatchQueue {
+    kQSpread = 0, kQZfft, kQRowFwd, kQCols, kQRowInv, kQZifft, kQGather,
+    kQReal, kQComb, kQEnergy, kNumQueues
+};
+
+struct BatchLaunch {           // one queue stage
+    const Item* items;          // device
+    int nitems;
+    int grid;                   // persistent blocks
+    size_t lds;                 // dynamic LDS bytes
+};
+
+template <typename T>
+struct BatchArgs {
+    const SysDesc<T>* sys;      // device
+    int nsys;
+    int P;
+    long long ntot;
+    const int* sys_of;          // packed particle -> system
+    long long ncl, ncb;         // total lex / block cells
+    int* key_lex; int* key_blk; int* slot_lex; int* slot_blk;
+    int* cnt_lex; int* cnt_blk;
+    DevParticles<T> lex, blk;   // packed, start = global cell starts
+    void* scan_tmp; size_t scan_bytes;
+    T* wz; T* wxp; T* wyq;
+    const cplx<T>* tw;
+    T* phiF; T* EF; T* phiR; T* ER;
+    double* partials;
+    int* qctr;                  // kNumQueues counters
+    BatchLaunch q[kNumQueues];
+};
+
+template <typename T>
+int launch_batch(const BatchArgs<T>& a, const T* x, const T* q, T* phi, T* E,
+                 double* energy, unsigned flags, hipStream_t s);
+
+// Blocks of one queue kernel that fit on the device at once.
+template <typename T>
+int batch_occupancy(int queue, int P, size_t lds, int* blocks_per_cu);
 
 }  // namespace se1p

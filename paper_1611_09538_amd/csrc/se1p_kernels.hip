@@ -209,6 +209,22 @@ __device__ __forceinline__ void cell_of(T x, T y, T z, const Geo& g, T& zw,
     cz = min(max(cz, 0), g.M3 - 1);
 }
 
+// Lex and block cell keys of one particle.
+template <typename T>
+__device__ __forceinline__ void cell_keys(const T* __restrict__ xin, long long i,
+                                          const Geo& g, const BinGeo& bg,
+                                          int& kl, int& kb) {
+    T zw;
+    int cx, cy, cz;
+    cell_of<T>(xin[3 * i], xin[3 * i + 1], xin[3 * i + 2], g, zw, cx, cy, cz);
+    kl = (cz * g.M1 + cx) * g.M2 + cy;
+    const int bz = cz / bg.BZ, iz = cz - bz * bg.BZ;
+    const int bx = cx / bg.BX, ix = cx - bx * bg.BX;
+    const int by = cy / bg.BY, iy = cy - by * bg.BY;
+    const int b = (bz * bg.nbx + bx) * bg.nby + by;
+    kb = b * bg.cpb + (iz * bg.BX + ix) * bg.BY + iy;
+}
+
 template <typename T>
 __global__ void bin_keys_kernel(const T* __restrict__ xin, long long N, Geo g,
                                 BinGeo bg, int* __restrict__ key_lex,
@@ -219,15 +235,8 @@ __global__ void bin_keys_kernel(const T* __restrict__ xin, long long N, Geo g,
                                 int* __restrict__ cnt_blk) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    T zw;
-    int cx, cy, cz;
-    cell_of<T>(xin[3 * i], xin[3 * i + 1], xin[3 * i + 2], g, zw, cx, cy, cz);
-    const int kl = (cz * g.M1 + cx) * g.M2 + cy;
-    const int bz = cz / bg.BZ, iz = cz - bz * bg.BZ;
-    const int bx = cx / bg.BX, ix = cx - bx * bg.BX;
-    const int by = cy / bg.BY, iy = cy - by * bg.BY;
-    const int b = (bz * bg.nbx + bx) * bg.nby + by;
-    const int kb = b * bg.cpb + (iz * bg.BX + ix) * bg.BY + iy;
+    int kl, kb;
+    cell_keys<T>(xin, i, g, bg, kl, kb);
     key_lex[i] = kl;
     key_blk[i] = kb;
     slot_lex[i] = atomicAdd(&cnt_lex[kl], 1);
@@ -264,11 +273,10 @@ __global__ void bin_sort_cells_kernel(long long ncell,
 }
 
 template <typename T>
-__global__ void bin_gather_kernel(const T* __restrict__ xin,
-                                  const T* __restrict__ qin, long long N,
-                                  Geo g, DevParticles<T> o) {
-    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N) return;
+__device__ __forceinline__ void bin_gather_one(const T* __restrict__ xin,
+                                               const T* __restrict__ qin,
+                                               long long p, const Geo& g,
+                                               const DevParticles<T>& o) {
     const int i = o.perm[p];
     const T x = xin[3 * (long long)i], y = xin[3 * (long long)i + 1];
     T zw;
@@ -278,9 +286,21 @@ __global__ void bin_gather_kernel(const T* __restrict__ xin,
     o.y[p] = y;
     o.z[p] = zw;
     o.q[p] = qin[i];
+    o.tx[p] = (T)((double)x * g.inv_h - (double)cx);
+    o.ty[p] = (T)((double)y * g.inv_h - (double)cy);
+    o.tz[p] = (T)((double)zw * g.inv_h - (double)cz);
     o.cx[p] = cx;
     o.cy[p] = cy;
     o.cz[p] = cz;
+}
+
+template <typename T>
+__global__ void bin_gather_kernel(const T* __restrict__ xin,
+                                  const T* __restrict__ qin, long long N,
+                                  Geo g, DevParticles<T> o) {
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    bin_gather_one<T>(xin, qin, p, g, o);
 }
 
 // ------------------------------------------------------------------------
@@ -289,27 +309,36 @@ __global__ void bin_gather_kernel(const T* __restrict__ xin,
 // Per particle (lex order): z weights wz[P] (wave-uniform in the spread
 // kernel) and zero-padded x weights wxp[P + 2 kPad], q * y weights wyq.
 template <typename T, int P>
-__global__ void spread_weights_kernel(DevParticles<T> lx, long long N, Geo g,
-                                      T* __restrict__ wz, T* __restrict__ wxp,
-                                      T* __restrict__ wyq) {
+__device__ __forceinline__ void spread_weights_one(const DevParticles<T>& lx,
+                                                   long long p, const Geo& g,
+                                                   T* __restrict__ wz,
+                                                   T* __restrict__ wxp,
+                                                   T* __restrict__ wyq) {
     constexpr int PW = P + 2 * kPad;
-    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N) return;
     const T h = (T)g.h, a = (T)g.alpha;
-    const T x = lx.x[p], y = lx.y[p], z = lx.z[p], q = lx.q[p];
-    const int cx = lx.cx[p], cy = lx.cy[p], cz = lx.cz[p];
+    const T tx = lx.tx[p], ty = lx.ty[p], tz = lx.tz[p], q = lx.q[p];
+    // distance to grid point cx + 1 + u - P/2 (array index) in units of h
     for (int k = 0; k < PW; ++k) {
         const int u = k - kPad;
         const bool in = (u >= 0) && (u < P);
-        const T dx = x - (T)(cx + 1 + u - P / 2) * h;
-        const T dy = y - (T)(cy + 1 + u - P / 2) * h;
+        const T dx = (tx - (T)(1 + u - P / 2)) * h;
+        const T dy = (ty - (T)(1 + u - P / 2)) * h;
         wxp[p * PW + k] = in ? dexp<T>(-a * dx * dx) : (T)0;
         wyq[p * PW + k] = in ? q * dexp<T>(-a * dy * dy) : (T)0;
     }
     for (int d = 0; d < P; ++d) {
-        const T dz = z - (T)(cz - P / 2 + 1 + d) * h;
+        const T dz = (tz - (T)(1 + d - P / 2)) * h;
         wz[p * P + d] = dexp<T>(-a * dz * dz);
     }
+}
+
+template <typename T, int P>
+__global__ void spread_weights_kernel(DevParticles<T> lx, long long N, Geo g,
+                                      T* __restrict__ wz, T* __restrict__ wxp,
+                                      T* __restrict__ wyq) {
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    spread_weights_one<T, P>(lx, p, g, wz, wxp, wyq);
 }
 
 // One wave owns the (x, y) pencils [X0, X0+8) x [Y0, Y0+8) and the z cells
@@ -320,16 +349,16 @@ __global__ void spread_weights_kernel(DevParticles<T> lx, long long N, Geo g,
 // of one partial grid tile the period exactly, so every partial grid is
 // fully written and the partial grids only need summing.
 template <typename T, int P>
-__global__ __launch_bounds__(64) void spread_kernel(
+__device__ __forceinline__ void spread_body(
     const T* __restrict__ wz, const T* __restrict__ wxp,
     const T* __restrict__ wyq, const int* __restrict__ pcy,
     const int* __restrict__ cstart, T* __restrict__ Hpart,
-    long long pstride, Geo g, int CZ, int KP) {
+    long long pstride, const Geo& g, int CZ, int KP, int tbx, int tby,
+    int jc) {
     constexpr int PW = P + 2 * kPad;
     const int lane = threadIdx.x;
-    const int X0 = blockIdx.x * kSpreadTile;
-    const int Y0 = blockIdx.y * kSpreadTile;
-    const int jc = blockIdx.z;
+    const int X0 = tbx * kSpreadTile;
+    const int Y0 = tby * kSpreadTile;
     const int lx = X0 + (lane >> 3);
     const int ly = Y0 + (lane & 7);
     const int cz0 = jc * CZ;
@@ -394,6 +423,16 @@ __global__ __launch_bounds__(64) void spread_kernel(
     }
 }
 
+template <typename T, int P>
+__global__ __launch_bounds__(64) void spread_kernel(
+    const T* __restrict__ wz, const T* __restrict__ wxp,
+    const T* __restrict__ wyq, const int* __restrict__ pcy,
+    const int* __restrict__ cstart, T* __restrict__ Hpart,
+    long long pstride, Geo g, int CZ, int KP) {
+    spread_body<T, P>(wz, wxp, wyq, pcy, cstart, Hpart, pstride, g, CZ, KP,
+                      blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 template <typename T>
 __global__ void reduce_partials_kernel(const T* __restrict__ Hp, int KP,
                                        long long pstride, long long n, T scale,
@@ -411,10 +450,10 @@ __global__ void reduce_partials_kernel(const T* __restrict__ Hp, int KP,
 // Forward real FFT along z of kZfftCols columns per block; columns 2t and
 // 2t+1 share one complex transform.  Sums the KP partial grids on load.
 template <typename T>
-__global__ __launch_bounds__(256) void zfft_kernel(
+__device__ __forceinline__ void zfft_body(
     const T* __restrict__ H, int KP, long long pstride, T in_scale,
-    cplx<T>* __restrict__ Fz, Geo g, FftDesc d,
-    const cplx<T>* __restrict__ tw) {
+    cplx<T>* __restrict__ Fz, const Geo& g, const FftDesc& d,
+    const cplx<T>* __restrict__ tw, int cbk) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
     const int M3 = g.M3;
@@ -422,7 +461,7 @@ __global__ __launch_bounds__(256) void zfft_kernel(
     constexpr int CB = kZfftCols;
     cplx<T>* B = A + (CB / 2) * stride;
     const long long ncol = g.ncol;
-    const long long c0 = (long long)blockIdx.x * CB;
+    const long long c0 = (long long)cbk * CB;
     for (int idx = threadIdx.x; idx < CB * M3; idx += blockDim.x) {
         const int z = idx / CB, c = idx - z * CB;
         const long long col = c0 + c;
@@ -456,11 +495,19 @@ __global__ __launch_bounds__(256) void zfft_kernel(
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void zfft_kernel(
+    const T* __restrict__ H, int KP, long long pstride, T in_scale,
+    cplx<T>* __restrict__ Fz, Geo g, FftDesc d,
+    const cplx<T>* __restrict__ tw) {
+    zfft_body<T>(H, KP, pstride, in_scale, Fz, g, d, tw, blockIdx.x);
+}
+
 // Inverse real FFT along z; writes Ht[z][col] * out_scale.
 template <typename T>
-__global__ __launch_bounds__(256) void zifft_kernel(
-    const cplx<T>* __restrict__ Fz, T out_scale, T* __restrict__ Ht, Geo g,
-    FftDesc d, const cplx<T>* __restrict__ tw) {
+__device__ __forceinline__ void zifft_body(
+    const cplx<T>* __restrict__ Fz, T out_scale, T* __restrict__ Ht,
+    const Geo& g, const FftDesc& d, const cplx<T>* __restrict__ tw, int cbk) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
     const int M3 = g.M3;
@@ -468,7 +515,7 @@ __global__ __launch_bounds__(256) void zifft_kernel(
     constexpr int CB = kZfftCols;
     cplx<T>* B = A + (CB / 2) * stride;
     const long long ncol = g.ncol;
-    const long long c0 = (long long)blockIdx.x * CB;
+    const long long c0 = (long long)cbk * CB;
     const int half = M3 / 2;
     for (int idx = threadIdx.x; idx < M3 * (CB / 2); idx += blockDim.x) {
         const int k = idx / (CB / 2), t = idx - k * (CB / 2);
@@ -497,6 +544,13 @@ __global__ __launch_bounds__(256) void zifft_kernel(
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void zifft_kernel(
+    const cplx<T>* __restrict__ Fz, T out_scale, T* __restrict__ Ht, Geo g,
+    FftDesc d, const cplx<T>* __restrict__ tw) {
+    zifft_body<T>(Fz, out_scale, Ht, g, d, tw, blockIdx.x);
+}
+
 // ------------------------------------------------------------------------
 // k-space: slab transforms (eq. upsamplings: per-slab padded sizes)
 // ------------------------------------------------------------------------
@@ -504,19 +558,19 @@ constexpr int kRowsPerBlock = 4;
 
 // Zero-padded forward FFT along y of the Mt1 rows of slab blockIdx.y.
 template <typename T>
-__global__ __launch_bounds__(256) void rowfwd_kernel(
+__device__ __forceinline__ void rowfwd_body(
     const cplx<T>* __restrict__ Fz, cplx<T>* __restrict__ G,
-    const SlabDesc* __restrict__ slabs, Geo g,
-    const cplx<T>* __restrict__ tw) {
+    const SlabDesc* __restrict__ slabs, const Geo& g,
+    const cplx<T>* __restrict__ tw, int rb, int slab) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const SlabDesc sd = slabs[blockIdx.y];
+    const SlabDesc& sd = slabs[slab];   // by reference: no private copy
     const int n2 = sd.n2;
-    const int x0 = blockIdx.x * kRowsPerBlock;
+    const int x0 = rb * kRowsPerBlock;
     if (x0 >= g.Mt1) return;
     const int nr = min(kRowsPerBlock, g.Mt1 - x0);
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* B = A + kRowsPerBlock * n2;
-    const cplx<T>* src = Fz + (long long)blockIdx.y * g.ncol;
+    const cplx<T>* src = Fz + (long long)slab * g.ncol;
     for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
         const int r = idx / n2, j = idx - r * n2;
         cplx<T> v;
@@ -531,6 +585,14 @@ __global__ __launch_bounds__(256) void rowfwd_kernel(
         const int r = idx / n2, j = idx - r * n2;
         dst[(long long)(x0 + r) * n2 + j] = X[r * n2 + j];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void rowfwd_kernel(
+    const cplx<T>* __restrict__ Fz, cplx<T>* __restrict__ G,
+    const SlabDesc* __restrict__ slabs, Geo g,
+    const cplx<T>* __restrict__ tw) {
+    rowfwd_body<T>(Fz, G, slabs, g, tw, blockIdx.x, blockIdx.y);
 }
 
 // Scaling factor (eq. scale_1p with G of eq. G_kappa_k), all constants and
@@ -560,13 +622,14 @@ constexpr int kColsPerBlock = 4;
 // Fused column pass: zero-padded FFT along x, scaling, inverse FFT along x,
 // restriction to the first Mt1 rows, for kColsPerBlock columns ky.
 template <typename T>
-__global__ __launch_bounds__(256) void cols_kernel(
-    cplx<T>* __restrict__ G, const SlabDesc* __restrict__ slabs, Geo g,
-    const cplx<T>* __restrict__ tw, const T* __restrict__ S0) {
+__device__ __forceinline__ void cols_body(
+    cplx<T>* __restrict__ G, const SlabDesc* __restrict__ slabs, const Geo& g,
+    const cplx<T>* __restrict__ tw, const T* __restrict__ S0, int cb,
+    int slab) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const SlabDesc sd = slabs[blockIdx.y];
+    const SlabDesc& sd = slabs[slab];   // by reference: no private copy
     const int n1 = sd.n1, n2 = sd.n2;
-    const int k0 = blockIdx.x * kColsPerBlock;
+    const int k0 = cb * kColsPerBlock;
     if (k0 >= n2) return;
     const int nc = min(kColsPerBlock, n2 - k0);
     const int stride = n1 + 1;
@@ -598,16 +661,23 @@ __global__ __launch_bounds__(256) void cols_kernel(
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void cols_kernel(
+    cplx<T>* __restrict__ G, const SlabDesc* __restrict__ slabs, Geo g,
+    const cplx<T>* __restrict__ tw, const T* __restrict__ S0) {
+    cols_body<T>(G, slabs, g, tw, S0, blockIdx.x, blockIdx.y);
+}
+
 // Inverse FFT along y, restriction to the first Mt2 columns.
 template <typename T>
-__global__ __launch_bounds__(256) void rowinv_kernel(
+__device__ __forceinline__ void rowinv_body(
     const cplx<T>* __restrict__ G, cplx<T>* __restrict__ Fz,
-    const SlabDesc* __restrict__ slabs, Geo g,
-    const cplx<T>* __restrict__ tw) {
+    const SlabDesc* __restrict__ slabs, const Geo& g,
+    const cplx<T>* __restrict__ tw, int rb, int slab) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const SlabDesc sd = slabs[blockIdx.y];
+    const SlabDesc& sd = slabs[slab];   // by reference: no private copy
     const int n2 = sd.n2;
-    const int x0 = blockIdx.x * kRowsPerBlock;
+    const int x0 = rb * kRowsPerBlock;
     if (x0 >= g.Mt1) return;
     const int nr = min(kRowsPerBlock, g.Mt1 - x0);
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -619,11 +689,19 @@ __global__ __launch_bounds__(256) void rowinv_kernel(
     }
     __syncthreads();
     cplx<T>* X = fft_lds<T>(A, B, nr, n2, sd.d2, tw + sd.d2.twoff, +1);
-    cplx<T>* dst = Fz + (long long)blockIdx.y * g.ncol;
+    cplx<T>* dst = Fz + (long long)slab * g.ncol;
     for (int idx = threadIdx.x; idx < nr * g.Mt2; idx += blockDim.x) {
         const int r = idx / g.Mt2, j = idx - r * g.Mt2;
         dst[(long long)(x0 + r) * g.Mt2 + j] = X[r * n2 + j];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void rowinv_kernel(
+    const cplx<T>* __restrict__ G, cplx<T>* __restrict__ Fz,
+    const SlabDesc* __restrict__ slabs, Geo g,
+    const cplx<T>* __restrict__ tw) {
+    rowinv_body<T>(G, Fz, slabs, g, tw, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------------------------
@@ -642,18 +720,18 @@ __global__ __launch_bounds__(256) void rowinv_kernel(
 constexpr int kGatherStage = 12; // staged plane values per lane in flight
 
 template <typename T, int P>
-__global__ __launch_bounds__(64) void gather_kernel(
-    const T* __restrict__ Ht, const T* __restrict__ px,
-    const T* __restrict__ py, const T* __restrict__ pz,
+__device__ __forceinline__ void gather_body(
+    const T* __restrict__ Ht, const T* __restrict__ ptx,
+    const T* __restrict__ pty, const T* __restrict__ ptz,
     const int* __restrict__ pcx, const int* __restrict__ pcy,
     const int* __restrict__ pcz, const int* __restrict__ perm,
-    const int* __restrict__ cstart, Geo g, BinGeo bg, int CH, T scale,
-    T* __restrict__ phi_out, T* __restrict__ E_out) {
+    const int* __restrict__ cstart, const Geo& g, const BinGeo& bg, int CH,
+    T scale, T* __restrict__ phi_out, T* __restrict__ E_out, int bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     constexpr int HP = P / 2;         // the y window is swept in two halves
-    const int b = blockIdx.x / CH;
-    const int slot = blockIdx.x - b * CH;
+    const int b = bid / CH;
+    const int slot = bid - b * CH;
     const int byk = b % bg.nby;
     const int tmp = b / bg.nby;
     const int bxk = tmp % bg.nbx;
@@ -676,7 +754,7 @@ __global__ __launch_bounds__(64) void gather_kernel(
         const int p = c0 + lane;
         const bool act = p < e;
         const int pp = act ? p : e - 1;
-        const T x = px[pp], y = py[pp], z = pz[pp];
+        const T tx = ptx[pp], ty = pty[pp], tz = ptz[pp];
         const int ox = pcx[pp] - bxk * bg.BX;
         const int oy = pcy[pp] - byk * bg.BY;
         const int oz = pcz[pp] - bzk * bg.BZ;
@@ -691,8 +769,9 @@ __global__ __launch_bounds__(64) void gather_kernel(
         const int nplanes = ozmax - ozmin + P;
 
         // distances from the particle to the first point of its window
-        const T dx0 = x - (T)(X0u + ox - P / 2) * h;
-        const T dy0 = y - (T)(Y0u + oy - P / 2) * h;
+        // (array index cx + 1 - P/2), from the offset inside its cell
+        const T dx0 = (tx - (T)(1 - P / 2)) * h;
+        const T dy0 = (ty - (T)(1 - P / 2)) * h;
         // Gaussian-gridding recurrence seeds (FP64): value and ratio at the
         // window start and at the start of the second half in y
         T wx0 = 0, rx0 = 0, wyA = 0, ryA = 0, wyB = 0, ryB = 0;
@@ -737,7 +816,7 @@ __global__ __launch_bounds__(64) void gather_kernel(
             const int uz = ozmin + ip;
             const int dzi = uz - oz;
             const bool zin = act && dzi >= 0 && dzi < P;
-            const T dz = z - (T)(zl0 + uz) * h;
+            const T dz = (tz - (T)(dzi + 1 - P / 2)) * h;
             const T wzv = zin ? dexp<T>(-a * dz * dz) : (T)0;
             const T tz = dz * wzv;
             if (__any(zin)) {
@@ -809,6 +888,18 @@ __global__ __launch_bounds__(64) void gather_kernel(
     }
 }
 
+template <typename T, int P>
+__global__ __launch_bounds__(64) void gather_kernel(
+    const T* __restrict__ Ht, const T* __restrict__ ptx,
+    const T* __restrict__ pty, const T* __restrict__ ptz,
+    const int* __restrict__ pcx, const int* __restrict__ pcy,
+    const int* __restrict__ pcz, const int* __restrict__ perm,
+    const int* __restrict__ cstart, Geo g, BinGeo bg, int CH, T scale,
+    T* __restrict__ phi_out, T* __restrict__ E_out) {
+    gather_body<T, P>(Ht, ptx, pty, ptz, pcx, pcy, pcz, perm, cstart, g, bg, CH,
+                      scale, phi_out, E_out, blockIdx.x);
+}
+
 // ------------------------------------------------------------------------
 // real-space sum over the cell list (eq. ewald1p_real, eq. force_real)
 // ------------------------------------------------------------------------
@@ -864,12 +955,13 @@ __device__ __forceinline__ void pair_terms<float>(float r2, float xi,
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void realspace_kernel(
-    DevParticles<T> blk, DevParticles<T> lx, Geo g, BinGeo bg, int CH, T xi,
-    T rc, int R, T* __restrict__ phi_out, T* __restrict__ E_out) {
+__device__ __forceinline__ void realspace_body(
+    const DevParticles<T>& blk, const DevParticles<T>& lx, const Geo& g,
+    const BinGeo& bg, int CH, T xi, T rc, int R, T* __restrict__ phi_out,
+    T* __restrict__ E_out, int bid) {
     __shared__ T cx_[64], cy_[64], cz_[64], cq_[64];
-    const int b = blockIdx.x / CH;
-    const int slot = blockIdx.x - b * CH;
+    const int b = bid / CH;
+    const int slot = bid - b * CH;
     const int s0 = blk.start[(long long)b * bg.cpb];
     const int e0 = blk.start[(long long)(b + 1) * bg.cpb];
     const int lane = threadIdx.x;
@@ -984,21 +1076,32 @@ __global__ __launch_bounds__(64) void realspace_kernel(
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(64) void realspace_kernel(
+    DevParticles<T> blk, DevParticles<T> lx, Geo g, BinGeo bg, int CH, T xi,
+    T rc, int R, T* __restrict__ phi_out, T* __restrict__ E_out) {
+    realspace_body<T>(blk, lx, g, bg, CH, xi, rc, R, phi_out, E_out, blockIdx.x);
+}
+
 // ------------------------------------------------------------------------
 // totals and energy
 // ------------------------------------------------------------------------
 constexpr int kCombineThreads = 256;
 
+// Totals of the particles [p0 + 256 blk, ...) below p0 + N, and their
+// energy partial sum into *partial.
 template <typename T>
-__global__ __launch_bounds__(kCombineThreads) void combine_kernel(
-    long long N, const T* __restrict__ q, const T* __restrict__ phiF,
-    const T* __restrict__ EF, const T* __restrict__ phiR,
-    const T* __restrict__ ER, double self_c, unsigned flags,
-    T* __restrict__ phi, T* __restrict__ E, double* __restrict__ partials) {
+__device__ __forceinline__ void combine_body(
+    long long p0, long long N, const T* __restrict__ q,
+    const T* __restrict__ phiF, const T* __restrict__ EF,
+    const T* __restrict__ phiR, const T* __restrict__ ER, double self_c,
+    unsigned flags, T* __restrict__ phi, T* __restrict__ E,
+    double* __restrict__ partial, int blk) {
     __shared__ double red[kCombineThreads];
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long li = (long long)blk * kCombineThreads + threadIdx.x;
+    const long long i = p0 + li;
     double u = 0.0;
-    if (i < N) {
+    if (li < N) {
         const T qi = q[i];
         T ph = 0;
         if (flags & 1u) ph += phiF[i];
@@ -1021,11 +1124,21 @@ __global__ __launch_bounds__(kCombineThreads) void combine_kernel(
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) *partial = red[0];
 }
 
-__global__ __launch_bounds__(256) void energy_final_kernel(
-    const double* __restrict__ partials, int n, double* __restrict__ energy) {
+template <typename T>
+__global__ __launch_bounds__(kCombineThreads) void combine_kernel(
+    long long N, const T* __restrict__ q, const T* __restrict__ phiF,
+    const T* __restrict__ EF, const T* __restrict__ phiR,
+    const T* __restrict__ ER, double self_c, unsigned flags,
+    T* __restrict__ phi, T* __restrict__ E, double* __restrict__ partials) {
+    combine_body<T>(0, N, q, phiF, EF, phiR, ER, self_c, flags, phi, E,
+                    partials + blockIdx.x, blockIdx.x);
+}
+
+__device__ __forceinline__ void energy_body(const double* __restrict__ partials,
+                                            int n, double* __restrict__ energy) {
     __shared__ double red[256];
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) s += partials[i];
@@ -1036,6 +1149,11 @@ __global__ __launch_bounds__(256) void energy_final_kernel(
         __syncthreads();
     }
     if (threadIdx.x == 0) *energy = 0.5 * red[0];
+}
+
+__global__ __launch_bounds__(256) void energy_final_kernel(
+    const double* __restrict__ partials, int n, double* __restrict__ energy) {
+    energy_body(partials, n, energy);
 }
 
 // ------------------------------------------------------------------------
@@ -1069,6 +1187,223 @@ __global__ __launch_bounds__(256) void check_kernel(
     if (threadIdx.x == 0) {
         atomicAdd(&qsum[0], r1[0]);
         atomicAdd(&qsum[1], r2[0]);
+    }
+}
+
+// ------------------------------------------------------------------------
+// batches: every system of a batch in one launch per stage
+// ------------------------------------------------------------------------
+// Particle-wise stages run over the packed particles and look their system
+// up; grid-shaped stages are persistent: a fixed set of blocks pulls
+// (system, tile) items from a global counter until the queue is empty, so
+// uneven systems balance across the chip without one launch per system.
+// Items are ordered by decreasing estimated cost.
+__device__ __forceinline__ int next_item(int* __restrict__ ctr) {
+    __shared__ int s_item;
+    __syncthreads();                 // the previous item is done with LDS
+    if (threadIdx.x == 0) s_item = atomicAdd(ctr, 1);
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(s_item);
+}
+
+template <typename T>
+__global__ void bbin_keys_kernel(const T* __restrict__ xin, long long N,
+                                 const int* __restrict__ sys_of,
+                                 const SysDesc<T>* __restrict__ sys,
+                                 int* __restrict__ key_lex,
+                                 int* __restrict__ key_blk,
+                                 int* __restrict__ slot_lex,
+                                 int* __restrict__ slot_blk,
+                                 int* __restrict__ cnt_lex,
+                                 int* __restrict__ cnt_blk) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const SysDesc<T>& sd = sys[sys_of[i]];
+    int kl, kb;
+    cell_keys<T>(xin, i, sd.g, sd.bg, kl, kb);
+    kl += (int)sd.cl0;
+    kb += (int)sd.cb0;
+    key_lex[i] = kl;
+    key_blk[i] = kb;
+    slot_lex[i] = atomicAdd(&cnt_lex[kl], 1);
+    slot_blk[i] = atomicAdd(&cnt_blk[kb], 1);
+}
+
+// Sorted position p belongs to the same system as its input index.
+template <typename T>
+__global__ void bbin_gather_kernel(const T* __restrict__ xin,
+                                   const T* __restrict__ qin, long long N,
+                                   const int* __restrict__ sys_of,
+                                   const SysDesc<T>* __restrict__ sys,
+                                   DevParticles<T> o) {
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    bin_gather_one<T>(xin, qin, p, sys[sys_of[p]].g, o);
+}
+
+template <typename T, int P>
+__global__ void bspread_weights_kernel(DevParticles<T> lx, long long N,
+                                       const int* __restrict__ sys_of,
+                                       const SysDesc<T>* __restrict__ sys,
+                                       T* __restrict__ wz, T* __restrict__ wxp,
+                                       T* __restrict__ wyq) {
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    spread_weights_one<T, P>(lx, p, sys[sys_of[p]].g, wz, wxp, wyq);
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(64) void bspread_kernel(
+    const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
+    int nitems, int* __restrict__ ctr, const T* __restrict__ wz,
+    const T* __restrict__ wxp, const T* __restrict__ wyq,
+    const int* __restrict__ pcy, const int* __restrict__ cstart) {
+    for (;;) {
+        const int it = next_item(ctr);
+        if (it >= nitems) return;
+        const Item w = items[it];
+        const SysDesc<T>& sd = sys[w.sys];
+        const Geo g = sd.g;
+        spread_body<T, P>(wz, wxp, wyq, pcy, cstart + sd.cl0, sd.Hpart,
+                          sd.pstride, g, sd.CZ, sd.KP, w.a, w.b, w.c);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void bzfft_kernel(
+    const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
+    int nitems, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
+    for (;;) {
+        const int it = next_item(ctr);
+        if (it >= nitems) return;
+        const Item w = items[it];
+        const SysDesc<T>& sd = sys[w.sys];
+        const Geo g = sd.g;
+        zfft_body<T>(sd.Hpart, sd.KP, sd.pstride, (T)1, sd.Fz, g, sd.dz, tw, w.a);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void browfwd_kernel(
+    const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
+    int nitems, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
+    for (;;) {
+        const int it = next_item(ctr);
+        if (it >= nitems) return;
+        const Item w = items[it];
+        const SysDesc<T>& sd = sys[w.sys];
+        const Geo g = sd.g;
+        rowfwd_body<T>(sd.Fz, sd.G, sd.slabs, g, tw, w.a, w.b);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void bcols_kernel(
+    const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
+    int nitems, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
+    for (;;) {
+        const int it = next_item(ctr);
+        if (it >= nitems) return;
+        const Item w = items[it];
+        const SysDesc<T>& sd = sys[w.sys];
+        const Geo g = sd.g;
+        cols_body<T>(sd.G, sd.slabs, g, tw, sd.S0, w.a, w.b);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void browinv_kernel(
+    const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
+    int nitems, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
+    for (;;) {
+        const int it = next_item(ctr);
+        if (it >= nitems) return;
+        const Item w = items[it];
+        const SysDesc<T>& sd = sys[w.sys];
+        const Geo g = sd.g;
+        rowinv_body<T>(sd.G, sd.Fz, sd.slabs, g, tw, w.a, w.b);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void bzifft_kernel(
+    const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
+    int nitems, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
+    for (;;) {
+        const int it = next_item(ctr);
+        if (it >= nitems) return;
+        const Item w = items[it];
+        const SysDesc<T>& sd = sys[w.sys];
+        const Geo g = sd.g;
+        zifft_body<T>(sd.Fz, (T)1, sd.Ht, g, sd.dz, tw, w.a);
+    }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(64) void bgather_kernel(
+    const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
+    int nitems, int* __restrict__ ctr, DevParticles<T> blk,
+    T* __restrict__ phi_out, T* __restrict__ E_out) {
+    for (;;) {
+        const int it = next_item(ctr);
+        if (it >= nitems) return;
+        const Item w = items[it];
+        const SysDesc<T>& sd = sys[w.sys];
+        const Geo g = sd.g;
+        const BinGeo bg = sd.bg;
+        gather_body<T, P>(sd.Ht, blk.tx, blk.ty, blk.tz, blk.cx, blk.cy, blk.cz,
+                          blk.perm, blk.start + sd.cb0, g, bg, bg.CH, (T)1,
+                          phi_out, E_out, w.a);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void brealspace_kernel(
+    const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
+    int nitems, int* __restrict__ ctr, DevParticles<T> blk,
+    DevParticles<T> lx, T* __restrict__ phi_out, T* __restrict__ E_out) {
+    for (;;) {
+        const int it = next_item(ctr);
+        if (it >= nitems) return;
+        const Item w = items[it];
+        const SysDesc<T>& sd = sys[w.sys];
+        const Geo g = sd.g;
+        const BinGeo bg = sd.bg;
+        DevParticles<T> b = blk, l = lx;
+        b.start = blk.start + sd.cb0;
+        l.start = lx.start + sd.cl0;
+        realspace_body<T>(b, l, g, bg, 4 * bg.CH, (T)sd.xi, (T)sd.rc, sd.R,
+                          phi_out, E_out, w.a);
+    }
+}
+
+// item (s, blk): particles [p0 + 256 blk, ...) of system s
+template <typename T>
+__global__ __launch_bounds__(kCombineThreads) void bcombine_kernel(
+    const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
+    int nitems, int* __restrict__ ctr, const T* __restrict__ q,
+    const T* __restrict__ phiF, const T* __restrict__ EF,
+    const T* __restrict__ phiR, const T* __restrict__ ER, unsigned flags,
+    T* __restrict__ phi, T* __restrict__ E, double* __restrict__ partials) {
+    for (;;) {
+        const int it = next_item(ctr);
+        if (it >= nitems) return;
+        const Item w = items[it];
+        const SysDesc<T>& sd = sys[w.sys];
+        const unsigned f = sd.rs ? flags : (flags & ~2u);
+        combine_body<T>(sd.p0, sd.n, q, phiF, EF, phiR, ER, sd.self_c, f, phi,
+                        E, partials + sd.e0 + w.a, w.a);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void benergy_kernel(
+    const SysDesc<T>* __restrict__ sys, int nsys,
+    const double* __restrict__ partials, double* __restrict__ energy) {
+    for (int s = blockIdx.x; s < nsys; s += gridDim.x) {
+        const SysDesc<T>& sd = sys[s];
+        energy_body(partials + sd.e0, sd.ncomb, energy + s);
+        __syncthreads();
     }
 }
 
@@ -1214,7 +1549,7 @@ static int gather_p(const T* Ht, const DevParticles<T>& blk, const Geo& g,
     (void)Uy;
     const size_t lds = 2 * (size_t)Ux * bg.ldy * sizeof(T);
     hipLaunchKernelGGL((gather_kernel<T, P>), dim3(nb), dim3(64), lds, s, Ht,
-                       blk.x, blk.y, blk.z, blk.cx, blk.cy, blk.cz, blk.perm,
+                       blk.tx, blk.ty, blk.tz, blk.cx, blk.cy, blk.cz, blk.perm,
                        blk.start, g, bg, bg.CH, scale, phi_out, E_out);
     SE1P_CHECK_LAUNCH();
     return 0;
@@ -1274,6 +1609,137 @@ int launch_check(const T* x, const T* q, long long N, double L1, double L2,
     return 0;
 }
 
+// ---- batches --------------------------------------------------------------
+template <typename T, int P>
+static int batch_p(const BatchArgs<T>& a, const T* x, const T* q, T* phi,
+                   T* E, double* energy, unsigned flags, hipStream_t s) {
+    const long long N = a.ntot;
+    int rc;
+    // counts and queue counters are cleared by kernels (no memset nodes if
+    // the sequence is captured in a graph)
+    if ((rc = launch_fill_int(a.cnt_lex, a.ncl + 1, 0, s))) return rc;
+    if ((rc = launch_fill_int(a.cnt_blk, a.ncb + 1, 0, s))) return rc;
+    if ((rc = launch_fill_int(a.qctr, kNumQueues, 0, s))) return rc;
+    hipLaunchKernelGGL(bbin_keys_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0, s,
+                       x, N, a.sys_of, a.sys, a.key_lex, a.key_blk, a.slot_lex,
+                       a.slot_blk, a.cnt_lex, a.cnt_blk);
+    SE1P_CHECK_LAUNCH();
+    size_t tb = a.scan_bytes;
+    if (hipcub::DeviceScan::ExclusiveSum(a.scan_tmp, tb, a.cnt_lex, a.lex.start,
+                                         (int)(a.ncl + 1), s) != hipSuccess)
+        return -5;
+    tb = a.scan_bytes;
+    if (hipcub::DeviceScan::ExclusiveSum(a.scan_tmp, tb, a.cnt_blk, a.blk.start,
+                                         (int)(a.ncb + 1), s) != hipSuccess)
+        return -5;
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(N, 256)), dim3(256), 0, s,
+                       N, a.key_lex, a.slot_lex, a.lex.start, a.lex.perm);
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(N, 256)), dim3(256), 0, s,
+                       N, a.key_blk, a.slot_blk, a.blk.start, a.blk.perm);
+    hipLaunchKernelGGL(bin_sort_cells_kernel, dim3(nblk(a.ncl, 256)), dim3(256),
+                       0, s, a.ncl, a.lex.start, a.lex.perm);
+    hipLaunchKernelGGL(bin_sort_cells_kernel, dim3(nblk(a.ncb, 256)), dim3(256),
+                       0, s, a.ncb, a.blk.start, a.blk.perm);
+    hipLaunchKernelGGL(bbin_gather_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0,
+                       s, x, q, N, a.sys_of, a.sys, a.lex);
+    hipLaunchKernelGGL(bbin_gather_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0,
+                       s, x, q, N, a.sys_of, a.sys, a.blk);
+    SE1P_CHECK_LAUNCH();
+    const BatchLaunch* L = a.q;
+    if (flags & 1u) {
+        hipLaunchKernelGGL((bspread_weights_kernel<T, P>), dim3(nblk(N, 128)),
+                           dim3(128), 0, s, a.lex, N, a.sys_of, a.sys, a.wz,
+                           a.wxp, a.wyq);
+        hipLaunchKernelGGL((bspread_kernel<T, P>), dim3(L[kQSpread].grid),
+                           dim3(64), L[kQSpread].lds, s, a.sys, L[kQSpread].items,
+                           L[kQSpread].nitems, a.qctr + kQSpread, a.wz, a.wxp,
+                           a.wyq, a.lex.cy, a.lex.start);
+        SE1P_CHECK_LAUNCH();
+        hipLaunchKernelGGL(bzfft_kernel<T>, dim3(L[kQZfft].grid), dim3(256),
+                           L[kQZfft].lds, s, a.sys, L[kQZfft].items,
+                           L[kQZfft].nitems, a.qctr + kQZfft, a.tw);
+        hipLaunchKernelGGL(browfwd_kernel<T>, dim3(L[kQRowFwd].grid), dim3(256),
+                           L[kQRowFwd].lds, s, a.sys, L[kQRowFwd].items,
+                           L[kQRowFwd].nitems, a.qctr + kQRowFwd, a.tw);
+        hipLaunchKernelGGL(bcols_kernel<T>, dim3(L[kQCols].grid), dim3(256),
+                           L[kQCols].lds, s, a.sys, L[kQCols].items,
+                           L[kQCols].nitems, a.qctr + kQCols, a.tw);
+        hipLaunchKernelGGL(browinv_kernel<T>, dim3(L[kQRowInv].grid), dim3(256),
+                           L[kQRowInv].lds, s, a.sys, L[kQRowInv].items,
+                           L[kQRowInv].nitems, a.qctr + kQRowInv, a.tw);
+        hipLaunchKernelGGL(bzifft_kernel<T>, dim3(L[kQZifft].grid), dim3(256),
+                           L[kQZifft].lds, s, a.sys, L[kQZifft].items,
+                           L[kQZifft].nitems, a.qctr + kQZifft, a.tw);
+        SE1P_CHECK_LAUNCH();
+        hipLaunchKernelGGL((bgather_kernel<T, P>), dim3(L[kQGather].grid),
+                           dim3(64), L[kQGather].lds, s, a.sys, L[kQGather].items,
+                           L[kQGather].nitems, a.qctr + kQGather, a.blk, a.phiF,
+                           a.EF);
+        SE1P_CHECK_LAUNCH();
+    }
+    if ((flags & 2u) && L[kQReal].nitems > 0) {
+        hipLaunchKernelGGL(brealspace_kernel<T>, dim3(L[kQReal].grid), dim3(64),
+                           0, s, a.sys, L[kQReal].items, L[kQReal].nitems,
+                           a.qctr + kQReal, a.blk, a.lex, a.phiR, a.ER);
+        SE1P_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(bcombine_kernel<T>, dim3(L[kQComb].grid),
+                       dim3(kCombineThreads), 0, s, a.sys, L[kQComb].items,
+                       L[kQComb].nitems, a.qctr + kQComb, q, a.phiF, a.EF,
+                       a.phiR, a.ER, flags & 7u, phi, E, a.partials);
+    SE1P_CHECK_LAUNCH();
+    if (energy) {
+        hipLaunchKernelGGL(benergy_kernel<T>, dim3(a.nsys), dim3(256), 0, s,
+                           a.sys, a.nsys, a.partials, energy);
+        SE1P_CHECK_LAUNCH();
+    }
+    return 0;
+}
+
+template <typename T>
+int launch_batch(const BatchArgs<T>& a, const T* x, const T* q, T* phi, T* E,
+                 double* energy, unsigned flags, hipStream_t s) {
+    switch (a.P) {
+#define SE1P_BATCH_CASE(PP) \
+    case PP: return batch_p<T, PP>(a, x, q, phi, E, energy, flags, s);
+        SE1P_P_CASES(SE1P_BATCH_CASE)
+#undef SE1P_BATCH_CASE
+        default: return -8;
+    }
+}
+
+template <typename T, int P>
+static int occ_p(int queue, size_t lds, int* bpc) {
+    const void* f = nullptr;
+    int bs = 256;
+    switch (queue) {
+        case kQSpread: f = (const void*)bspread_kernel<T, P>; bs = 64; break;
+        case kQZfft: f = (const void*)bzfft_kernel<T>; break;
+        case kQRowFwd: f = (const void*)browfwd_kernel<T>; break;
+        case kQCols: f = (const void*)bcols_kernel<T>; break;
+        case kQRowInv: f = (const void*)browinv_kernel<T>; break;
+        case kQZifft: f = (const void*)bzifft_kernel<T>; break;
+        case kQGather: f = (const void*)bgather_kernel<T, P>; bs = 64; break;
+        case kQReal: f = (const void*)brealspace_kernel<T>; bs = 64; break;
+        case kQComb: f = (const void*)bcombine_kernel<T>; bs = kCombineThreads; break;
+        default: return -1;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, f, bs, lds) != hipSuccess)
+        return -5;
+    return 0;
+}
+
+template <typename T>
+int batch_occupancy(int queue, int P, size_t lds, int* blocks_per_cu) {
+    switch (P) {
+#define SE1P_OCC_CASE(PP) \
+    case PP: return occ_p<T, PP>(queue, lds, blocks_per_cu);
+        SE1P_P_CASES(SE1P_OCC_CASE)
+#undef SE1P_OCC_CASE
+        default: return -8;
+    }
+}
+
 // explicit instantiations
 #define SE1P_INST(T)                                                           \
     template int launch_bin<T>(const T*, const T*, long long, const Geo&,       \
@@ -1300,7 +1766,10 @@ int launch_check(const T* x, const T* q, long long N, double L1, double L2,
                                    const T*, const T*, double, unsigned, T*,    \
                                    T*, double*, int, double*, hipStream_t);     \
     template int launch_check<T>(const T*, const T*, long long, double, double, \
-                                 int*, double*, hipStream_t);
+                                 int*, double*, hipStream_t);                   \
+    template int launch_batch<T>(const BatchArgs<T>&, const T*, const T*, T*,  \
+                                 T*, double*, unsigned, hipStream_t);           \
+    template int batch_occupancy<T>(int, int, size_t, int*);
 
 SE1P_INST(double)
 SE1P_INST(float)

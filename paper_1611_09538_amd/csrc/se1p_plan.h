@@ -1,0 +1,86 @@
+// se1p_plan.h -- host-side plan state shared by the single-system entry
+// points (se1p_host.cpp) and the batched ones (se1p_batch.cpp).  Internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <vector>
+
+#include "../../include/se1p.h"
+#include "se1p_internal.h"
+
+using se1p::BinGeo;
+using se1p::FftDesc;
+using se1p::Geo;
+using se1p::SlabDesc;
+
+// Geometry, tables and (for single-system plans) the device workspace.
+struct se1p_plan {
+    se1p_params prm;
+    int prec = 0;           // SE1P_FP64 / SE1P_FP32
+    size_t es = 8;          // element size
+    long long n_max = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    Geo g{};
+    BinGeo bg{};
+    double cg = 0.0;        // (2 xi^2 / (pi eta))^{3/2}
+    double R = 0.0;
+    int M1 = 0, M2 = 0;
+    int n0[2] = {0, 0}, nl[2] = {0, 0};
+    int nslab = 0;
+    int CZ = 0, KP = 0;
+    std::vector<SlabDesc> slabs;
+    FftDesc dz{};
+    long long tw_elems = 0;
+    long long slab_elems = 0;
+    std::map<int, int> twoff;   // FFT length -> twiddle offset (complex elements)
+
+    // device memory (single allocation, carved)
+    void* base = nullptr;
+    size_t ws_bytes = 0;
+    int *key_lex = nullptr, *key_blk = nullptr, *slot_lex = nullptr, *slot_blk = nullptr;
+    int *cnt_lex = nullptr, *cnt_blk = nullptr;
+    int *lex_i[5] = {}, *blk_i[5] = {};   // cx, cy, cz, perm, start
+    void *lex_f[7] = {}, *blk_f[7] = {};  // x, y, z, q, tx, ty, tz
+    void* scan_tmp = nullptr;
+    size_t scan_bytes = 0;
+    void *wz = nullptr, *wxp = nullptr, *wyq = nullptr;
+    void* Hpart = nullptr;
+    long long pstride = 0;
+    void* Fz = nullptr;
+    void* G = nullptr;
+    void* Ht = nullptr;
+    void* S0 = nullptr;
+    void* tw = nullptr;
+    SlabDesc* d_slabs = nullptr;
+    void *phiF = nullptr, *EF = nullptr, *phiR = nullptr, *ER = nullptr;
+    double* partials = nullptr;
+    int nblk_comb = 0;
+    int* flag = nullptr;
+    double* qsum = nullptr;
+
+    // stage timing: events[call][boundary], boundaries 0..SE1P_NSTAGE
+    int timing = 0;
+    int tcalls = 0;
+    std::vector<hipEvent_t> tev;
+    std::vector<unsigned char> tmask;   // stages run per call
+};
+
+namespace se1p {
+size_t scan_temp_bytes(long long n);
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// Parameter checks shared by plans and batches.
+int plan_check_params(const se1p_params& p);
+// Grid geometry, padded FFT sizes, slab descriptors, tiling and twiddle
+// offsets of one system (no device memory).
+int plan_geometry(se1p_plan& pl, const se1p_params& p, long long n_max);
+// Host tables of a planned system: twiddles exp(-2 pi i k/n) for every length
+// in pl.twoff (interleaved re/im, laid out by pl.twoff) and the FP64
+// scaling table of slab n3 = 0, n0[0] x n0[1].
+void plan_tables(const se1p_plan& pl, std::vector<double>& tw, std::vector<double>& s0);
+}  // namespace se1p

@@ -35,6 +35,7 @@ SELF = 4
 ALL = 7
 CHECK_INPUT = 16
 NO_NEUTRAL = 32
+BATCH_EAGER = 64
 
 
 class SE1PError(RuntimeError):
@@ -90,12 +91,43 @@ class PlanInfo(ctypes.Structure):
                 "n_max": self.n_max, "workspace_bytes": self.workspace_bytes}
 
 
+class CostModel(ctypes.Structure):
+    _fields_ = [
+        ("pair_ns", ctypes.c_double),
+        ("grid_ns", ctypes.c_double),
+        ("fft_ns", ctypes.c_double),
+        ("particle_ns", ctypes.c_double),
+        ("system_ns", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("nsys", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("P", ctypes.c_int),
+        ("n_total", ctypes.c_longlong),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("items", ctypes.c_int * 10),
+        ("grid", ctypes.c_int * 10),
+        ("graph_captures", ctypes.c_int),
+    ]
+
+
+QUEUES = ["spread", "zfft", "rowfwd", "cols", "rowinv", "zifft", "gather",
+          "realspace", "combine"]
+
 # every symbol include/se1p.h declares
 EXPORTS = [
     "se1p_suggest_params", "se1p_plan_create", "se1p_plan_destroy",
     "se1p_plan_get_info", "se1p_set_stream", "se1p_eval", "se1p_spread",
     "se1p_kspace_solve", "se1p_gather", "se1p_error_string", "se1p_version",
-    "se1p_timing_enable", "se1p_timing_read",
+    "se1p_timing_enable", "se1p_timing_read", "se1p_calibrate",
+    "se1p_autotune", "se1p_batch_create", "se1p_batch_destroy",
+    "se1p_batch_eval", "se1p_batch_get_info", "se1p_batch_system_info",
 ]
 
 NSTAGE = 6
@@ -141,6 +173,24 @@ def _lib():
     lib.se1p_timing_enable.argtypes = [vp, i]
     lib.se1p_timing_read.restype = i
     lib.se1p_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i)]
+    lib.se1p_calibrate.restype = i
+    lib.se1p_calibrate.argtypes = [d, i, i, vp, ctypes.POINTER(CostModel)]
+    lib.se1p_autotune.restype = i
+    lib.se1p_autotune.argtypes = [d, i, ctypes.POINTER(d), ctypes.POINTER(ll),
+                                  ctypes.POINTER(d), i, i, ctypes.POINTER(CostModel),
+                                  ctypes.POINTER(Params)]
+    lib.se1p_batch_create.restype = i
+    lib.se1p_batch_create.argtypes = [i, ctypes.POINTER(Params), ctypes.POINTER(ll), vp,
+                                      ctypes.POINTER(vp)]
+    lib.se1p_batch_destroy.restype = i
+    lib.se1p_batch_destroy.argtypes = [vp]
+    lib.se1p_batch_eval.restype = i
+    lib.se1p_batch_eval.argtypes = [vp, vp, vp, vp, vp, vp, u]
+    lib.se1p_batch_get_info.restype = i
+    lib.se1p_batch_get_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    lib.se1p_batch_system_info.restype = i
+    lib.se1p_batch_system_info.argtypes = [vp, i, ctypes.POINTER(Params),
+                                           ctypes.POINTER(PlanInfo)]
     _LIB = lib
     return lib
 
@@ -306,3 +356,109 @@ class Plan:
         _check(_lib().se1p_gather(self._h, N, _ptr(x), _ptr(grid), _ptr(phi), _ptr(E)),
                "se1p_gather")
         return phi, E
+
+
+def autotune(tol, boxes, counts, Q=None, precision=FP32, P=12, model=None):
+    """Per-system parameters with the least predicted cost at tolerance tol
+    (host only).  boxes: (nsys, 3); counts: nsys; Q: nsys sums of q^2 or
+    None for unit charges; model: CostModel or None for the built-in one."""
+    n = len(counts)
+    bx = (ctypes.c_double * (3 * n))(*[float(v) for b in boxes for v in b])
+    ct = (ctypes.c_longlong * n)(*[int(c) for c in counts])
+    qq = None if Q is None else (ctypes.c_double * n)(*[float(v) for v in Q])
+    out = (Params * n)()
+    _check(_lib().se1p_autotune(float(tol), n, bx, ct, qq, int(precision), int(P),
+                                None if model is None else ctypes.byref(model), out),
+           "se1p_autotune")
+    return [out[k] for k in range(n)]
+
+
+def calibrate(tol, precision=FP32, P=12, stream=None) -> CostModel:
+    """Cost model measured on the current device (synchronises)."""
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    m = CostModel()
+    _check(_lib().se1p_calibrate(float(tol), int(precision), int(P),
+                                 ctypes.c_void_p(s.cuda_stream), ctypes.byref(m)),
+           "se1p_calibrate")
+    return m
+
+
+class Batch:
+    """Many independent systems evaluated together (one launch per stage,
+    persistent work queues, replayed as one HIP graph)."""
+
+    def __init__(self, params, counts, stream=None):
+        torch = _torch()
+        n = len(params)
+        if n != len(counts) or n == 0:
+            raise ValueError("params and counts must be non-empty and of equal length")
+        self.params = list(params)
+        self.counts = [int(c) for c in counts]
+        self.offsets = [0]
+        for c in self.counts:
+            self.offsets.append(self.offsets[-1] + c)
+        self.dtype = torch.float64 if params[0].precision == FP64 else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._stream = s
+        arr = (Params * n)(*self.params)
+        ct = (ctypes.c_longlong * n)(*self.counts)
+        h = ctypes.c_void_p()
+        _check(_lib().se1p_batch_create(n, arr, ct, ctypes.c_void_p(s.cuda_stream),
+                                        ctypes.byref(h)), "se1p_batch_create")
+        self._h = h
+
+    @property
+    def n_total(self):
+        return self.offsets[-1]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib().se1p_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        bi = BatchInfo()
+        _check(_lib().se1p_batch_get_info(self._h, ctypes.byref(bi)), "se1p_batch_get_info")
+        return {"nsys": bi.nsys, "precision": bi.precision, "P": bi.P,
+                "n_total": bi.n_total, "workspace_bytes": bi.workspace_bytes,
+                "items": {QUEUES[k]: bi.items[k] for k in range(len(QUEUES))},
+                "grid": {QUEUES[k]: bi.grid[k] for k in range(len(QUEUES))},
+                "graph_captures": bi.graph_captures}
+
+    def system_info(self, s):
+        p = Params()
+        pi = PlanInfo()
+        _check(_lib().se1p_batch_system_info(self._h, int(s), ctypes.byref(p),
+                                             ctypes.byref(pi)), "se1p_batch_system_info")
+        return p, pi.as_dict()
+
+    def eval_into(self, x, q, phi, E, U, flags=ALL, eager=False):
+        """Enqueue on the batch's stream into preallocated packed outputs."""
+        torch = _torch()
+        if torch.cuda.current_stream(self.device).cuda_stream != self._stream.cuda_stream:
+            raise RuntimeError("Batch calls must run on the stream it was created with")
+        if x.shape[0] != self.n_total or q.shape[0] != self.n_total:
+            raise ValueError("x and q must hold the packed particles of every system")
+        f = int(flags) | (BATCH_EAGER if eager else 0)
+        _check(_lib().se1p_batch_eval(self._h, _ptr(x), _ptr(q), _ptr(phi), _ptr(E),
+                                      _ptr(U), f), "se1p_batch_eval")
+
+    def eval(self, x, q, flags=ALL, eager=False):
+        """Returns packed (phi, E) and the per-system energies."""
+        torch = _torch()
+        x = x.to(self.dtype).contiguous()
+        q = q.to(device=x.device, dtype=self.dtype).contiguous().reshape(-1)
+        N = self.n_total
+        phi = torch.empty(N, dtype=self.dtype, device=x.device)
+        E = torch.empty((N, 3), dtype=self.dtype, device=x.device)
+        U = torch.empty(len(self.counts), dtype=torch.float64, device=x.device)
+        self.eval_into(x, q, phi, E, U, flags, eager)
+        return phi, E, U

@@ -50,11 +50,17 @@ CASES = {
                      seed=2, M3=64, P=24, nl=4, tol=1e-8, precision="fp64",
                      xi=25.0, sl=3.0, rc=0.16, pad_free=8),
     # Differentiation: N=2e5, 1x1x2 box (z long and periodic), +-1 charges.
+    # Same grid spacing and xi as fp64_1e5; the k3 spacing halves with the
+    # longer period, so twice the upsampled slabs and twice the padding.
     "grad_2e5": dict(n=200_000, box=(1.0, 1.0, 2.0), charges="pm1", seed=3,
-                     M3=128, P=24, tol=1e-8, precision="fp64"),
+                     M3=128, P=24, tol=1e-8, precision="fp64",
+                     xi=25.0, nl=8, sl=6.0, rc=0.17, pad_free=8),
     # Precision: N=1e6, 2x2x1 box, uniform charges, FP32, P=12, rel-RMS 1e-5.
+    # xi large enough that the real-space pairs stay few at this density
+    # (2.5e5 per unit volume); M3 follows xi at the 1e-5 Fourier bar.
     "fp32_1e6": dict(n=1_000_000, box=(2.0, 2.0, 1.0), charges="uniform",
-                     seed=4, M3=48, P=12, tol=1e-5, precision="fp32"),
+                     seed=4, M3=96, P=12, tol=1e-5, precision="fp32",
+                     xi=48.0, nl=8, sl=2.0, rc=0.069, pad_free=4),
 }
 
 

@@ -39,7 +39,8 @@ def test_version_and_error_strings():
 
 def test_suggest_params_follows_recipe():
     # cube, tolerance 1e-8 with M3 fixed: xi from the Fourier estimate,
-    # P from the approximation estimate, s_l from exp(-2 pi s_l Lt/L3) < tol
+    # P from the approximation estimate, s_l from
+    # exp(-2 pi (s_l - 1) Lt / L3) < tol
     p = se1p.suggest_params(1e-8, (1.0, 1.0, 1.0), 100000, 100000 / 3.0, M3=64)
     assert p.M3 == 64
     kinf = 32.0
@@ -51,7 +52,7 @@ def test_suggest_params_follows_recipe():
     assert A * math.exp(-0.95 ** 2 * math.pi * p.P / 2) < 1e-8
     h = 1.0 / 64
     Lt = 1.0 + p.P * h
-    assert math.exp(-2 * math.pi * p.s_l * Lt) <= 1e-8 * (1 + 1e-9)
+    assert math.exp(-2 * math.pi * (p.s_l - 1) * Lt) == pytest.approx(1e-8, rel=1e-9)
     assert p.n_l == round(64 / 10)
     assert p.s0 == pytest.approx(1 + math.sqrt(2))
     # real-space estimate (eq. trunc_error_estimate_real) at the chosen rc
