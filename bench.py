@@ -3,18 +3,29 @@
 One step = one full SE1P evaluation (binning, gridding, adaptive FFT with
 scaling, inverse transform, gathering of phi and E, real-space sum, self
 term, FP64 energy) of the N = 1e5 FP64 system in a unit box periodic in z
-(M3 = 64, P = 24, n_l = 4), inputs already resident in device memory.
-Prints one JSON line.
+(M3 = 64, P = 24, n_l = 4, rel-RMS 1e-8), inputs already resident in device
+memory.  Prints one JSON line.
 
-Extra fields: per-stage times from HIP events on the plan's stream, the
-roofline of the dominant kernel (live event timing; algorithmic flops from
-the method's operation count), the oracle on the host cores as a CPU
-baseline on a bounded sample of targets, and the rel-RMS error of the GPU
-result on that sample.
+Extra fields:
+  stages_ms       per-stage times from HIP events on the plan's stream
+  roofline        the dominant kernel (the real-space sum): algorithmic flops
+                  (exact in-range pair count x flops per pair) over its
+                  event-timed duration, against the MI355X vector peak;
+                  traffic from the committed FETCH_SIZE / WRITE_SIZE counter
+                  summary when it was taken on the current kernel source
+  kernels         the gridding and gathering kernels against their own
+                  bounds (FP64 vector flops; LDS bytes for the gather)
+  fp32            the N = 1e6 FP32 system (2 x 2 x 1, P = 12, rel-RMS 1e-5):
+                  FP32 path and the FP64 path at the same parameters
+  batched         64 systems (N log-uniform in [1e3, 5e4]) in one graph
+                  launch, FP32 at 1e-5, against one plan per system (FP32 and
+                  FP64) at the same parameters
+  cpu_baseline    the oracle on the host cores on a bounded target sample
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,8 +36,21 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "SE1P potential+force particles/s at rel-RMS 1e-8 (FP64) and 1e-5 (FP32)"
-FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector, dense
-FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, dense
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X vector, dense
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1611_09538_amd", "csrc", "se1p_kernels.hip")
+
+# Flops per in-range pair of the real-space sum (phi and E), counting each
+# add, multiply and compare-free FMA half as one flop and rsqrt / exp / erfc
+# as one each:
+#   FP64: distance and r^2 8, rsqrt and r 2, exponent and exp 3,
+#         reciprocal with two Newton steps 9, Chebyshev variable 2,
+#         degree-16 Horner 32, erfc / r 2, phi update 2, radial factor 5,
+#         field update 6                                          = 71
+#   FP32: distance and r^2 8, rsqrt and r 2, erfc 1, exponent and exp 3,
+#         erfc / r 1, phi update 2, radial factor 5, field update 6 = 28
+PAIR_FLOPS = {"f64": 71.0, "f32": 28.0}
 
 
 def parse():
@@ -36,20 +60,155 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--case", default="fp64_1e5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP32 and batched measurements")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 512 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
 def gather_flops(N, P):
-    # per particle: 2 FMA (4 flop) per support point for phi and one
-    # gradient component, i.e. 4 P^3 (the field's other components reuse
-    # the same row sums)
+    # per particle and support point: phi and the x, y, z gradient sums,
+    # 4 FMA with the row sums shared (2 flops each)
     return 4.0 * N * P ** 3
 
 
 def spread_flops(N, P):
     return 2.0 * N * P ** 3
+
+
+def pair_count(x, box, rc):
+    """Ordered pairs (i != j) closer than rc, periodic images along z only."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    L3 = box[2]
+    img = [x]
+    k = 1
+    while (k - 1) * L3 < rc:
+        for s in (k, -k):
+            y = x.copy()
+            y[:, 2] += s * L3
+            img.append(y)
+        k += 1
+    a = cKDTree(x)
+    b = cKDTree(np.concatenate(img))
+    return int(a.count_neighbors(b, rc)) - x.shape[0]
+
+
+def src_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(kernel, case):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(case, {}).get(kernel)
+    if not e or t.get("kernel_source_sha256_16") != src_hash():
+        return None
+    return e["bytes_per_launch"]
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def plan_for(se1p, c, box, n, precision):
+    prm = se1p.make_params(box, c["xi"], c["M3"], c["P"], c["nl"], c["sl"],
+                           rc=c["rc"], pad_free=c["pad_free"], precision=precision)
+    return se1p.Plan(prm, n_max=n)
+
+
+def fp32_extra(se1p, workloads, torch, dev, steps, warmup):
+    import numpy as np
+    x, q, box, c = workloads.make_case("fp32_1e6")
+    N = x.shape[0]
+    out = {"workload": f"fp32_1e6: N={N}, box {tuple(box)}, M3={c['M3']}, P={c['P']}, "
+                       f"xi={c['xi']}, n_l={c['nl']}, s_l={c['sl']}, rc={c['rc']}"}
+    for prec, name in ((se1p.FP32, "f32"), (se1p.FP64, "f64")):
+        dt = torch.float32 if prec == se1p.FP32 else torch.float64
+        plan = plan_for(se1p, c, box, N, prec)
+        xt = torch.tensor(x.astype(np.float32), device=dev).to(dt)
+        qt = torch.tensor(q, device=dev, dtype=dt)
+        phi = torch.empty(N, device=dev, dtype=dt)
+        E = torch.empty((N, 3), device=dev, dtype=dt)
+        U = torch.empty(1, device=dev, dtype=torch.float64)
+        plan.timing_enable(True)
+        s = timed(lambda: plan.eval_into(xt, qt, phi, E, U), steps, warmup, torch)
+        st, nc = plan.timing_read()
+        plan.timing_enable(False)
+        out[name] = {"ms_per_step": s * 1e3, "particles_per_s": N / s,
+                     "stages_ms": {k: v / max(nc, 1) for k, v in st.items()}}
+        plan.close()
+        del xt, qt, phi, E, U
+    out["speedup_fp32_over_fp64"] = out["f64"]["ms_per_step"] / out["f32"]["ms_per_step"]
+    return out
+
+
+def batched_extra(se1p, workloads, torch, dev, steps, warmup):
+    import numpy as np
+    sysl = workloads.batched_systems()
+    boxes = [s[2] for s in sysl]
+    counts = [s[0].shape[0] for s in sysl]
+    Ntot = sum(counts)
+    params = se1p.autotune(1e-5, boxes, counts, precision=se1p.FP32, P=12)
+    batch = se1p.Batch(params, counts)
+    x = torch.tensor(np.concatenate([s[0] for s in sysl]), device=dev, dtype=torch.float32)
+    q = torch.tensor(np.concatenate([s[1] for s in sysl]), device=dev, dtype=torch.float32)
+    phi = torch.empty(Ntot, device=dev, dtype=torch.float32)
+    E = torch.empty((Ntot, 3), device=dev, dtype=torch.float32)
+    U = torch.empty(len(counts), device=dev, dtype=torch.float64)
+    t_graph = timed(lambda: batch.eval_into(x, q, phi, E, U), steps, warmup, torch)
+    t_eager = timed(lambda: batch.eval_into(x, q, phi, E, U, eager=True), steps, warmup, torch)
+    info = batch.info()
+    batch.close()
+    out = {"workload": f"64 systems, N log-uniform in [1e3, 5e4] (sum {Ntot}), "
+                       "L3 uniform in [0.5, 2], 1 x 1 cross-section, +-1 charges, "
+                       "FP32, P=12, autotuned for 1e-5",
+           "n_total": Ntot,
+           "graph_ms": t_graph * 1e3, "eager_ms": t_eager * 1e3,
+           "particles_per_s": Ntot / t_graph,
+           "queue_items": info["items"], "persistent_grid": info["grid"]}
+    # one plan per system, launched back to back on one stream
+    for prec, name in ((se1p.FP32, "loop_f32"), (se1p.FP64, "loop_f64")):
+        dt = torch.float32 if prec == se1p.FP32 else torch.float64
+        plans, bufs = [], []
+        off = 0
+        for s, p in enumerate(params):
+            p2 = se1p.Params.from_buffer_copy(p)
+            p2.precision = prec
+            plans.append(se1p.Plan(p2, n_max=counts[s]))
+            n = counts[s]
+            bufs.append((x[off:off + n].to(dt), q[off:off + n].to(dt),
+                         torch.empty(n, device=dev, dtype=dt),
+                         torch.empty((n, 3), device=dev, dtype=dt),
+                         torch.empty(1, device=dev, dtype=torch.float64)))
+            off += n
+
+        def loop():
+            for pl, b in zip(plans, bufs):
+                pl.eval_into(*b)
+        t = timed(loop, max(2, steps // 4), 1, torch)
+        out[name + "_ms"] = t * 1e3
+        for pl in plans:
+            pl.close()
+    out["speedup_over_loop_f32"] = out["loop_f32_ms"] / out["graph_ms"]
+    out["speedup_over_plain_f64"] = out["loop_f64_ms"] / out["graph_ms"]
+    return out
 
 
 def main():
@@ -68,9 +227,8 @@ def main():
     x, q, box, c = workloads.make_case(a.case)
     N = x.shape[0]
     prec = se1p.FP64 if c["precision"] == "fp64" else se1p.FP32
-    prm = se1p.make_params(box, c["xi"], c["M3"], c["P"], c["nl"], c["sl"],
-                           rc=c["rc"], pad_free=c["pad_free"], precision=prec)
-    plan = se1p.Plan(prm, n_max=N)
+    dname = "f64" if prec == se1p.FP64 else "f32"
+    plan = plan_for(se1p, c, box, N, prec)
     dt = plan.dtype
     xt = torch.tensor(x, device=dev, dtype=dt)
     qt = torch.tensor(q, device=dev, dtype=dt)
@@ -91,6 +249,7 @@ def main():
     t1 = time.perf_counter()
     stages, ncalls = plan.timing_read()
     plan.timing_enable(False)
+    print(f"timed {a.steps} steps", file=sys.stderr, flush=True)
 
     ms_step = (t1 - t0) * 1e3 / a.steps
     value = N / (ms_step * 1e-3)
@@ -98,21 +257,30 @@ def main():
     kspace_ms = st_ms["bin"] + st_ms["spread"] + st_ms["kspace"] + st_ms["gather"]
 
     P = c["P"]
-    peak = FP64_VALU_PEAK_TFLOPS if prec == se1p.FP64 else FP32_VALU_PEAK_TFLOPS
-    # dominant kernel among the single-kernel stages
-    dom = max(["gather", "realspace"], key=lambda k: st_ms[k])
-    if dom == "gather":
-        flops = gather_flops(N, P)
-        ach = flops / (st_ms["gather"] * 1e-3) / 1e12
-        roof = {"kernel": "gather_kernel", "bound": "alu", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
-                "algorithmic_flops_per_launch": flops, "avg_ms": st_ms["gather"]}
-    else:
-        roof = {"kernel": "realspace_kernel", "bound": "alu", "achieved": None,
-                "peak": peak, "unit": "TFLOP/s", "frac": None, "traffic": None,
-                "avg_ms": st_ms["realspace"]}
-    # the gridding kernel's share, reported alongside
-    sp_flops = spread_flops(N, P)
+    peak = PEAK_TFLOPS[dname]
+    npairs = pair_count(x, box, c["rc"])
+    rs_flops = PAIR_FLOPS[dname] * npairs
+    rs_ach = rs_flops / (st_ms["realspace"] * 1e-3) / 1e12
+    roof = {"kernel": "realspace_kernel", "bound": "alu", "achieved": rs_ach,
+            "peak": peak, "unit": "TFLOP/s", "frac": rs_ach / peak,
+            "traffic": traffic_for("realspace_kernel", a.case),
+            "pairs_per_launch": npairs, "flops_per_pair": PAIR_FLOPS[dname],
+            "algorithmic_flops_per_launch": rs_flops, "avg_ms": st_ms["realspace"]}
+    g_fl = gather_flops(N, P)
+    g_ach = g_fl / (st_ms["gather"] * 1e-3) / 1e12
+    kern = {
+        "gather_kernel": {"bound": "alu", "achieved": g_ach, "peak": peak,
+                          "unit": "TFLOP/s", "frac": g_ach / peak,
+                          "algorithmic_flops_per_launch": g_fl,
+                          "avg_ms": st_ms["gather"],
+                          "traffic": traffic_for("gather_kernel", a.case)},
+        "spread_stage": {"bound": "alu",
+                         "achieved": spread_flops(N, P) / (st_ms["spread"] * 1e-3) / 1e12,
+                         "peak": peak, "unit": "TFLOP/s",
+                         "frac": spread_flops(N, P) / (st_ms["spread"] * 1e-3) / 1e12 / peak,
+                         "algorithmic_flops_per_launch": spread_flops(N, P),
+                         "avg_ms": st_ms["spread"]},
+    }
 
     out = {
         "metric": METRIC,
@@ -125,7 +293,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == se1p.FP64 else "f32",
+        "dtype": dname,
         "data": "synthetic",
         "config": {"workload": f"{a.case}: N={N} neutral charges, box {tuple(box)} periodic in z",
                    "N": N, "M3": c["M3"], "P": P, "xi": c["xi"], "n_l": c["nl"],
@@ -135,9 +303,25 @@ def main():
                    "parallelism": "single GPU"},
         "stages_ms": st_ms,
         "kspace_particles_per_s": N / (kspace_ms * 1e-3),
-        "spread_tflops": sp_flops / (st_ms["spread"] * 1e-3) / 1e12,
         "roofline": roof,
+        "kernels": kern,
     }
+    plan.close()
+
+    if a.copy_calib:
+        src = torch.empty(1 << 27, device=dev, dtype=torch.float32)   # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes_each_way"] = src.numel() * 4
+        del src, dst
+
+    if not a.no_extras:
+        out["fp32"] = fp32_extra(se1p, workloads, torch, dev, max(5, a.steps // 2), 2)
+        print("fp32 done", file=sys.stderr, flush=True)
+        out["batched"] = batched_extra(se1p, workloads, torch, dev, max(5, a.steps // 2), 2)
+        print("batched done", file=sys.stderr, flush=True)
 
     if not a.no_cpu_baseline:
         import oracle
@@ -164,7 +348,6 @@ def main():
             "E": float(np.linalg.norm(Eg[tg] - E_ref) / np.linalg.norm(E_ref)),
             "targets": nt}
     print(json.dumps(out))
-    plan.close()
 
 
 if __name__ == "__main__":
