@@ -192,11 +192,11 @@ int build_batch(se1p_batch& b) {
         const int Ux = bg.BX + P - 1;
         lds[kQGather] = std::max(lds[kQGather], 2 * (size_t)Ux * bg.ldy * es);
         if (pl.prm.rc > 0.0) {
+            // chunks of 16 consecutive targets of the system
             const double nb = rho / (g.h * g.h * g.h) * 4.0 / 3.0 * kPi *
                               std::pow(pl.prm.rc + g.h, 3.0);
-            const double cr = std::max(1.0, m / (4.0 * bg.CH)) * nb;
-            for (long long k = 0; k < nblk * 4 * bg.CH; ++k)
-                it[kQReal].push_back({cr, Item{s, (int)k, 0, 0}});
+            for (long long k = 0; k < (b.cnt[s] + 15) / 16; ++k)
+                it[kQReal].push_back({16.0 * nb, Item{s, (int)k, 0, 0}});
         }
         for (long long k = 0; k < (b.cnt[s] + 255) / 256; ++k)
             it[kQComb].push_back({1.0, Item{s, (int)k, 0, 0}});

@@ -209,6 +209,26 @@ __device__ __forceinline__ void cell_of(T x, T y, T z, const Geo& g, T& zw,
     cz = min(max(cz, 0), g.M3 - 1);
 }
 
+// Blocks of cells are numbered along a serpentine path (x reversed on odd
+// z planes, y reversed on odd rows), so consecutive blocks are always face
+// neighbours: a run of consecutive particles of the block order stays
+// spatially compact across block boundaries.
+__device__ __forceinline__ int block_index(int bz, int bx, int by, const BinGeo& bg) {
+    const int bxs = (bz & 1) ? bg.nbx - 1 - bx : bx;
+    const int row = bz * bg.nbx + bxs;
+    const int bys = (row & 1) ? bg.nby - 1 - by : by;
+    return row * bg.nby + bys;
+}
+__device__ __forceinline__ void block_coords(int b, const BinGeo& bg, int& bz,
+                                             int& bx, int& by) {
+    const int bys = b % bg.nby;
+    const int row = b / bg.nby;
+    const int bxs = row % bg.nbx;
+    bz = row / bg.nbx;
+    by = (row & 1) ? bg.nby - 1 - bys : bys;
+    bx = (bz & 1) ? bg.nbx - 1 - bxs : bxs;
+}
+
 // Lex and block cell keys of one particle.
 template <typename T>
 __device__ __forceinline__ void cell_keys(const T* __restrict__ xin, long long i,
@@ -221,8 +241,7 @@ __device__ __forceinline__ void cell_keys(const T* __restrict__ xin, long long i
     const int bz = cz / bg.BZ, iz = cz - bz * bg.BZ;
     const int bx = cx / bg.BX, ix = cx - bx * bg.BX;
     const int by = cy / bg.BY, iy = cy - by * bg.BY;
-    const int b = (bz * bg.nbx + bx) * bg.nby + by;
-    kb = b * bg.cpb + (iz * bg.BX + ix) * bg.BY + iy;
+    kb = block_index(bz, bx, by, bg) * bg.cpb + (iz * bg.BX + ix) * bg.BY + iy;
 }
 
 template <typename T>
@@ -732,10 +751,8 @@ __device__ __forceinline__ void gather_body(
     constexpr int HP = P / 2;         // the y window is swept in two halves
     const int b = bid / CH;
     const int slot = bid - b * CH;
-    const int byk = b % bg.nby;
-    const int tmp = b / bg.nby;
-    const int bxk = tmp % bg.nbx;
-    const int bzk = tmp / bg.nbx;
+    int bzk, bxk, byk;
+    block_coords(b, bg, bzk, bxk, byk);
     const int s = cstart[(long long)b * bg.cpb];
     const int e = cstart[(long long)(b + 1) * bg.cpb];
     const int X0u = bxk * bg.BX + 1;  // array index of the footprint start
@@ -903,22 +920,23 @@ __global__ __launch_bounds__(64) void gather_kernel(
 // ------------------------------------------------------------------------
 // real-space sum over the cell list (eq. ewald1p_real, eq. force_real)
 // ------------------------------------------------------------------------
-// One wave takes a chunk of up to 16 target particles of one block (the
-// gather's blocks); four lanes share a target and split its candidates.
-// Candidate sources are the cells within the cut-off of the chunk's cell
-// box, walked
-// as runs of the lex order (fixed z cell and x cell, a range of y cells
-// clipped to the cut-off sphere around the box; z wraps with the image
-// shift folded into the staged position).  Candidates are staged in LDS in
-// batches of 64.  A first pass sets, per lane, one bit per candidate of its
-// quarter within the cut-off; a second pass lets every lane pop its own
-// bits, so the erfc and exp run for in-range pairs only, with most lanes
-// busy.  The four partial sums of a target are added with lane shuffles.
+// One wave takes a chunk of 16 consecutive targets of the block order
+// (spatially compact: blocks of cells, cells in order inside a block); four
+// lanes share a target and split its candidates.  Candidate sources are the
+// cells within the cut-off of the chunk's cell box, walked as runs of the
+// lex order (fixed z cell and x cell, a range of y cells clipped to the
+// cut-off sphere around the box; z wraps with the image shift folded into
+// the staged position).  Candidates are staged in LDS in batches of 64, the
+// next batch's loads in flight while the current one is processed.  A first
+// pass sets, per lane, one bit per candidate of its quarter within the
+// cut-off; a second pass lets every lane pop its own bits, so the erfc and
+// exp run for in-range pairs only, with most lanes busy.  The four partial
+// sums of a target are added with lane shuffles.
 // erfc(xi r) / r and the radial field factor q (erfc(xi r)/r +
 // 2 xi/sqrt(pi) exp(-xi^2 r^2)) / r^2 of one pair.  FP64 shares the
 // exponential: erfc(x) = exp(-x^2) erfcx(x) with erfcx from the fitted
-// polynomial of erfcx_poly.h (relative error ~1e-14); FP32 uses the device
-// library's erfc and exp.
+// polynomial of erfcx_poly.h (relative error 6e-12); FP32 does the same
+// with a degree-8 float fit (2e-7).
 template <typename T>
 __device__ __forceinline__ void pair_terms(T r2, T xi, T xi2, T c_erf, T qn,
                                            T& ec, T& f);
@@ -950,20 +968,25 @@ __device__ __forceinline__ void pair_terms<float>(float r2, float xi,
                                                   float& f) {
     const float rinv = rsqrtf(r2);
     const float r = r2 * rinv;
-    ec = erfcf(xi * r) * rinv;
-    f = qn * (ec + c_erf * __expf(-xi2 * r2)) * (rinv * rinv);
+    const float x = fminf(xi * r, (float)kErfcxXmax);
+    const float e = __expf(-xi2 * r2);
+    const float t = __builtin_amdgcn_rcpf(1.0f + (float)kErfcxA * x);
+    const float cu = (float)(2.0 / (1.0 - kErfcxTmin));
+    const float u = fmaf(t, cu, (float)(-1.0 - kErfcxTmin * 2.0 / (1.0 - kErfcxTmin)));
+    float pv = kErfcxCF[kErfcxDegF];
+#pragma unroll
+    for (int k = kErfcxDegF - 1; k >= 0; --k) pv = fmaf(pv, u, kErfcxCF[k]);
+    ec = e * (t * pv) * rinv;
+    f = qn * (ec + c_erf * e) * (rinv * rinv);
 }
 
 template <typename T>
 __device__ __forceinline__ void realspace_body(
     const DevParticles<T>& blk, const DevParticles<T>& lx, const Geo& g,
-    const BinGeo& bg, int CH, T xi, T rc, int R, T* __restrict__ phi_out,
-    T* __restrict__ E_out, int bid) {
+    T xi, T rc, int R, T* __restrict__ phi_out, T* __restrict__ E_out,
+    int pbeg, int pend, int chunk) {
     __shared__ T cx_[64], cy_[64], cz_[64], cq_[64];
-    const int b = bid / CH;
-    const int slot = bid - b * CH;
-    const int s0 = blk.start[(long long)b * bg.cpb];
-    const int e0 = blk.start[(long long)(b + 1) * bg.cpb];
+    __shared__ int rows_s[64], rows_e[64], rows_h[64];
     const int lane = threadIdx.x;
     const int tq = lane >> 2;         // target of this lane within the chunk
     const int kq = lane & 3;          // quarter of each candidate batch
@@ -973,12 +996,12 @@ __device__ __forceinline__ void realspace_body(
     const T L3 = (T)g.L3;
     const double rcell2 = (double)rc * (double)rc / (g.h * g.h);
 
-    // chunks of 16 targets; four lanes share a target and split its
-    // candidates
-    for (int c0 = s0 + 16 * slot; c0 < e0; c0 += 16 * CH) {
-        const int p = c0 + tq;
-        const bool act = p < e0;
-        const int pp = act ? p : e0 - 1;
+    // one chunk of 16 consecutive targets of the block order; four lanes
+    // share a target and split its candidates
+    {
+        const int p = pbeg + 16 * chunk + tq;
+        const bool act = p < pend;
+        const int pp = act ? p : pend - 1;
         const T xt = blk.x[pp], yt = blk.y[pp], zt = blk.z[pp];
         // cell box of the chunk's targets
         int mnx = act ? blk.cx[pp] : 1 << 20, mxx = act ? blk.cx[pp] : -(1 << 20);
@@ -994,10 +1017,8 @@ __device__ __forceinline__ void realspace_body(
         const int by0 = __builtin_amdgcn_readfirstlane(mny), by1 = __builtin_amdgcn_readfirstlane(mxy);
         const int bz0 = __builtin_amdgcn_readfirstlane(mnz), bz1 = __builtin_amdgcn_readfirstlane(mxz);
         T phi = 0, ex = 0, ey = 0, ez = 0;
-        int fill = 0;
 
         auto process = [&](int n) {
-            __syncthreads();
             // pass 1: one bit per in-range candidate j = kq + 4 i
             unsigned int mask = 0u;
             for (int i = 0; 4 * i < n; ++i) {
@@ -1023,41 +1044,115 @@ __device__ __forceinline__ void realspace_body(
                     ez += f * dz;
                 }
             }
-            __syncthreads();
         };
 
-        for (int czu = bz0 - R; czu <= bz1 + R; ++czu) {
-            const int gz = max(0, max(bz0 - czu, czu - bz1) - 1);
-            const int czw = imod(czu, g.M3);
-            const T shift = (T)((czu - czw) / g.M3) * L3;
-            for (int cxn = max(0, bx0 - R); cxn <= min(g.M1 - 1, bx1 + R); ++cxn) {
+        // Candidate rows: fixed z cell and x cell, the y cells of the row
+        // clipped to the cut-off sphere around the chunk's cell box.  Rows
+        // are set up 64 at a time by the lanes (bounds from the lex cell
+        // starts, image shift in periods) and walked from LDS, so the wave
+        // does not wait on one dependent load per row.
+        const int xlo = max(0, bx0 - R), xhi = min(g.M1 - 1, bx1 + R);
+        const int nxr = xhi - xlo + 1;
+        const int nrows = (bz1 - bz0 + 1 + 2 * R) * nxr;
+        auto load_rows = [&](int base) {
+            const int r = base + lane;
+            int rs = 0, re = 0, rsh = 0;
+            if (r < nrows) {
+                const int czu = bz0 - R + r / nxr;
+                const int cxn = xlo + r % nxr;
+                const int gz = max(0, max(bz0 - czu, czu - bz1) - 1);
                 const int gx = max(0, max(bx0 - cxn, cxn - bx1) - 1);
                 const double rem = rcell2 - (double)gz * gz - (double)gx * gx;
-                if (rem < 0.0) continue;
-                const int gy = (int)sqrt(rem) + 1;
-                const int ylo = max(0, by0 - gy), yhi = min(g.M2 - 1, by1 + gy);
-                const long long cb = ((long long)czw * g.M1 + cxn) * g.M2;
-                int s = lx.start[cb + ylo];
-                const int e = lx.start[cb + yhi + 1];
-                while (s < e) {
-                    const int take = min(e - s, 64 - fill);
-                    if (lane < take) {
-                        const int n = s + lane;
-                        cx_[fill + lane] = lx.x[n];
-                        cy_[fill + lane] = lx.y[n];
-                        cz_[fill + lane] = lx.z[n] + shift;
-                        cq_[fill + lane] = lx.q[n];
-                    }
-                    fill += take;
-                    s += take;
-                    if (fill == 64) {
-                        process(64);
-                        fill = 0;
-                    }
+                if (rem >= 0.0) {
+                    const int gy = (int)sqrt(rem) + 1;
+                    const int ylo = max(0, by0 - gy), yhi = min(g.M2 - 1, by1 + gy);
+                    const int czw = imod(czu, g.M3);
+                    const long long cb = ((long long)czw * g.M1 + cxn) * g.M2;
+                    rs = lx.start[cb + ylo];
+                    re = lx.start[cb + yhi + 1];
+                    rsh = (czu - czw) / g.M3;
                 }
             }
+            __syncthreads();           // earlier rows no longer read
+            rows_s[lane] = rs;
+            rows_e[lane] = re;
+            rows_h[lane] = rsh;
+            __syncthreads();
+        };
+        int rbase = 0, rk = 0;         // uniform: first row of the LDS block, row in it
+        bool more = nrows > 0;
+        int s_cur = 0, e_cur = 0, h_cur = 0;
+        if (more) {
+            load_rows(0);
+            s_cur = __builtin_amdgcn_readfirstlane(rows_s[0]);
+            e_cur = __builtin_amdgcn_readfirstlane(rows_e[0]);
+            h_cur = __builtin_amdgcn_readfirstlane(rows_h[0]);
         }
-        if (fill > 0) process(fill);
+        // The next batch of up to 64 candidates: lane l takes candidate
+        // cand (-1: none) of image shift csh periods.  Returns the count.
+        auto next_batch = [&](int& cand, int& csh) {
+            int fill = 0;
+            cand = -1;
+            csh = 0;
+            while (fill < 64 && more) {
+                if (s_cur >= e_cur) {
+                    if (++rk == 64) {
+                        rbase += 64;
+                        rk = 0;
+                        if (rbase < nrows) load_rows(rbase);
+                    }
+                    if (rbase + rk >= nrows) {
+                        more = false;
+                        break;
+                    }
+                    s_cur = __builtin_amdgcn_readfirstlane(rows_s[rk]);
+                    e_cur = __builtin_amdgcn_readfirstlane(rows_e[rk]);
+                    h_cur = __builtin_amdgcn_readfirstlane(rows_h[rk]);
+                    continue;
+                }
+                const int take = min(e_cur - s_cur, 64 - fill);
+                if (lane >= fill && lane < fill + take) {
+                    cand = s_cur + lane - fill;
+                    csh = h_cur;
+                }
+                fill += take;
+                s_cur += take;
+            }
+            return fill;
+        };
+        // Software pipeline: the loads of the next batch are in flight
+        // while the current batch is processed from LDS.
+        int cand, csh;
+        int nA = next_batch(cand, csh);
+        T ax = 0, ay = 0, az = 0, aq = 0;
+        if (cand >= 0) {
+            ax = lx.x[cand];
+            ay = lx.y[cand];
+            az = lx.z[cand] + (T)csh * L3;
+            aq = lx.q[cand];
+        }
+        while (nA > 0) {
+            __syncthreads();           // the previous batch is no longer read
+            cx_[lane] = ax;
+            cy_[lane] = ay;
+            cz_[lane] = az;
+            cq_[lane] = aq;
+            __syncthreads();
+            const int nB = next_batch(cand, csh);
+            T bx_ = 0, by_ = 0, bz_ = 0, bq_ = 0;
+            if (cand >= 0) {
+                bx_ = lx.x[cand];
+                by_ = lx.y[cand];
+                bz_ = lx.z[cand] + (T)csh * L3;
+                bq_ = lx.q[cand];
+            }
+            process(nA);
+            ax = bx_;
+            ay = by_;
+            az = bz_;
+            aq = bq_;
+            nA = nB;
+        }
         // sum the four lanes of each target
 #pragma unroll
         for (int m = 1; m <= 2; m <<= 1) {
@@ -1077,10 +1172,10 @@ __device__ __forceinline__ void realspace_body(
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void realspace_kernel(
-    DevParticles<T> blk, DevParticles<T> lx, Geo g, BinGeo bg, int CH, T xi,
-    T rc, int R, T* __restrict__ phi_out, T* __restrict__ E_out) {
-    realspace_body<T>(blk, lx, g, bg, CH, xi, rc, R, phi_out, E_out, blockIdx.x);
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void realspace_kernel(
+    DevParticles<T> blk, DevParticles<T> lx, Geo g, int N, T xi, T rc, int R,
+    T* __restrict__ phi_out, T* __restrict__ E_out) {
+    realspace_body<T>(blk, lx, g, xi, rc, R, phi_out, E_out, 0, N, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------
@@ -1358,7 +1453,7 @@ __global__ __launch_bounds__(64) void bgather_kernel(
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void brealspace_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void brealspace_kernel(
     const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
     int nitems, int* __restrict__ ctr, DevParticles<T> blk,
     DevParticles<T> lx, T* __restrict__ phi_out, T* __restrict__ E_out) {
@@ -1368,12 +1463,10 @@ __global__ __launch_bounds__(64) void brealspace_kernel(
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
-        const BinGeo bg = sd.bg;
-        DevParticles<T> b = blk, l = lx;
-        b.start = blk.start + sd.cb0;
+        DevParticles<T> l = lx;
         l.start = lx.start + sd.cl0;
-        realspace_body<T>(b, l, g, bg, 4 * bg.CH, (T)sd.xi, (T)sd.rc, sd.R,
-                          phi_out, E_out, w.a);
+        realspace_body<T>(blk, l, g, (T)sd.xi, (T)sd.rc, sd.R, phi_out, E_out,
+                          (int)sd.p0, (int)(sd.p0 + sd.n), w.a);
     }
 }
 
@@ -1573,12 +1666,11 @@ template <typename T>
 int launch_realspace(const DevParticles<T>& lex, const DevParticles<T>& blk,
                      long long N, const Geo& g, const BinGeo& bg, double xi,
                      double rc, T* phi_out, T* E_out, hipStream_t s) {
-    (void)N;
+    (void)bg;
     const int R = (int)ceil(rc / g.h);
-    const int CHr = 4 * bg.CH;   // chunks of 16 targets
-    const unsigned nb = (unsigned)(bg.nbx * bg.nby * bg.nbz) * CHr;
+    const unsigned nb = (unsigned)((N + 15) / 16);   // chunks of 16 targets
     hipLaunchKernelGGL(realspace_kernel<T>, dim3(nb), dim3(64), 0, s, blk, lex,
-                       g, bg, CHr, (T)xi, (T)rc, R, phi_out, E_out);
+                       g, (int)N, (T)xi, (T)rc, R, phi_out, E_out);
     SE1P_CHECK_LAUNCH();
     return 0;
 }

@@ -13,7 +13,8 @@ from dataclasses import dataclass, field
 from typing import Optional
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libse1p.so")
+# SE1P_LIB may name another build of the same library (profiling variants)
+LIB_PATH = os.environ.get("SE1P_LIB") or os.path.join(_HERE, "libse1p.so")
 
 # error codes / flags (include/se1p.h)
 OK = 0

@@ -127,11 +127,12 @@ def test_small_fp64_matches_oracle():
     dE = EF.cpu().numpy() - (r["E_Fk"] + r["E_F0"])
     assert np.linalg.norm(dphi) / np.linalg.norm(phi_ref) < 1e-8
     assert np.linalg.norm(dE) / np.linalg.norm(E_ref) < 1e-8
-    # real space with the same cut-off: same sum, rounding only
+    # real space with the same cut-off: the same sum; the kernel's erfc is
+    # exp(-x^2) times a fitted erfcx with relative error 6e-12 per pair
     phiR, ER, _ = plan.eval(xt, qt, flags=se1p.REAL)
     torch.cuda.synchronize()
-    assert _relrms(phiR.cpu().numpy(), r["phi_R"]) < 1e-13
-    assert _relrms(ER.cpu().numpy(), r["E_R"]) < 1e-13
+    assert _relrms(phiR.cpu().numpy(), r["phi_R"]) < 6e-12
+    assert _relrms(ER.cpu().numpy(), r["E_R"]) < 6e-12
     phiS, _, _ = plan.eval(xt, qt, flags=se1p.SELF)
     torch.cuda.synchronize()
     assert np.allclose(phiS.cpu().numpy(), r["phi_self"], rtol=1e-15, atol=0)
