@@ -206,7 +206,7 @@ void choose_spread(se1p_plan& pl) {
         for (int k = need; k <= ncz; ++k)
             if (ncz % k == 0) { KP = k; break; }
         if (KP < 0) continue;
-        const double waves = (double)tiles * ncz;
+        const double waves = (double)tiles * ncz * spread_waves(P);
         const double fill = std::min(1.0, waves / 2048.0);
         const double score = fill * 4.0 - 0.05 * KP;
         if (score > bestScore) { bestScore = score; bestCZ = CZ; bestKP = KP; }

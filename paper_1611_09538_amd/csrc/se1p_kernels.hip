@@ -360,13 +360,16 @@ __global__ void spread_weights_kernel(DevParticles<T> lx, long long N, Geo g,
     spread_weights_one<T, P>(lx, p, g, wz, wxp, wyq);
 }
 
-// One wave owns the (x, y) pencils [X0, X0+8) x [Y0, Y0+8) and the z cells
-// [cz0, cz0+CZ).  acc[d] holds grid point z = cz - P/2 + 1 + d while cell cz
-// is processed; after cell cz the point z = cz - P/2 + 1 is final for this
-// chunk and is written out.  Chunk jc writes KP*CZ consecutive z planes
-// (mod M3) of partial grid jc % KP; with M3/CZ a multiple of KP, the chunks
-// of one partial grid tile the period exactly, so every partial grid is
-// fully written and the partial grids only need summing.
+// A workgroup of spread_waves(P) waves owns the (x, y) pencils [X0, X0+8) x
+// [Y0, Y0+8) (one lane per pencil) and the z cells [cz0, cz0+CZ); the waves
+// split the particles of each cell row between them.  acc[d] holds grid
+// point z = cz - P/2 + 1 + d while cell cz is processed; after cell cz the
+// point z = cz - P/2 + 1 is final for this chunk: the waves' values are
+// summed in LDS in a fixed order and written out.  Chunk jc writes KP*CZ
+// consecutive z planes (mod M3) of partial grid jc % KP; with M3/CZ a
+// multiple of KP, the chunks of one partial grid tile the period exactly, so
+// every partial grid is fully written and the partial grids only need
+// summing.
 template <typename T, int P>
 __device__ __forceinline__ void spread_body(
     const T* __restrict__ wz, const T* __restrict__ wxp,
@@ -375,7 +378,10 @@ __device__ __forceinline__ void spread_body(
     long long pstride, const Geo& g, int CZ, int KP, int tbx, int tby,
     int jc) {
     constexpr int PW = P + 2 * kPad;
-    const int lane = threadIdx.x;
+    constexpr int W = spread_waves(P);
+    __shared__ T red[W > 1 ? W : 1][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int X0 = tbx * kSpreadTile;
     const int Y0 = tby * kSpreadTile;
     const int lx = X0 + (lane >> 3);
@@ -392,6 +398,23 @@ __device__ __forceinline__ void spread_body(
 #pragma unroll
     for (int d = 0; d < P; ++d) acc[d] = (T)0;
 
+    // sum one finished plane over the waves and write it
+    auto finish = [&](T v, int zplane) {
+        if constexpr (W == 1) {
+            if (writer) out[(long long)imod(zplane, g.M3) * g.ncol] = v;
+        } else {
+            red[wv][lane] = v;
+            __syncthreads();
+            if (wv == 0 && writer) {
+                T sum = red[0][lane];
+#pragma unroll
+                for (int w = 1; w < W; ++w) sum += red[w][lane];
+                out[(long long)imod(zplane, g.M3) * g.ncol] = sum;
+            }
+            __syncthreads();
+        }
+    };
+
     for (int ci = 0; ci < CZ; ++ci) {
         const int cz = cz0 + ci;
         if (cxlo <= cxhi && cylo <= cyhi) {
@@ -400,15 +423,15 @@ __device__ __forceinline__ void spread_body(
                 const int s = cstart[cb + cylo];
                 const int e = cstart[cb + cyhi + 1];
                 const int offx = lx - (cx + 1) + kPad;
-                int p = s;
-                for (; p + 1 < e; p += 2) {
-                    const int cyA = pcy[p], cyB = pcy[p + 1];
+                int p = s + wv;
+                for (; p + W < e; p += 2 * W) {
+                    const int cyA = pcy[p], cyB = pcy[p + W];
                     const T cA = wxp[(long long)p * PW + offx] *
                                  wyq[(long long)p * PW + ly - (cyA + 1) + kPad];
-                    const T cB = wxp[(long long)(p + 1) * PW + offx] *
-                                 wyq[(long long)(p + 1) * PW + ly - (cyB + 1) + kPad];
+                    const T cB = wxp[(long long)(p + W) * PW + offx] *
+                                 wyq[(long long)(p + W) * PW + ly - (cyB + 1) + kPad];
                     const T* __restrict__ zA = wz + (long long)p * P;
-                    const T* __restrict__ zB = zA + P;
+                    const T* __restrict__ zB = wz + (long long)(p + W) * P;
 #pragma unroll
                     for (int d = 0; d < P; ++d) acc[d] = fma(cA, zA[d], acc[d]);
 #pragma unroll
@@ -425,7 +448,7 @@ __device__ __forceinline__ void spread_body(
             }
         }
         // plane zstart + ci is final
-        if (writer) out[(long long)imod(zstart + ci, g.M3) * g.ncol] = acc[0];
+        finish(acc[0], zstart + ci);
 #pragma unroll
         for (int d = 0; d < P - 1; ++d) acc[d] = acc[d + 1];
         acc[P - 1] = (T)0;
@@ -433,17 +456,16 @@ __device__ __forceinline__ void spread_body(
     // remaining planes of this chunk's KP*CZ-plane window
     const int base = zstart + CZ;
 #pragma unroll
-    for (int d = 0; d < P - 1; ++d) {
-        if (writer) out[(long long)imod(base + d, g.M3) * g.ncol] = acc[d];
-    }
+    for (int d = 0; d < P - 1; ++d) finish(acc[d], base + d);
     const int tail = KP * CZ - CZ;
-    for (int d = P - 1; d < tail; ++d) {
-        if (writer) out[(long long)imod(base + d, g.M3) * g.ncol] = (T)0;
+    if (wv == 0 && writer) {
+        for (int d = P - 1; d < tail; ++d)
+            out[(long long)imod(base + d, g.M3) * g.ncol] = (T)0;
     }
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(64) void spread_kernel(
+__global__ __launch_bounds__(64 * spread_waves(P)) void spread_kernel(
     const T* __restrict__ wz, const T* __restrict__ wxp,
     const T* __restrict__ wyq, const int* __restrict__ pcy,
     const int* __restrict__ cstart, T* __restrict__ Hpart,
@@ -1348,7 +1370,7 @@ __global__ void bspread_weights_kernel(DevParticles<T> lx, long long N,
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(64) void bspread_kernel(
+__global__ __launch_bounds__(64 * spread_waves(P)) void bspread_kernel(
     const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
     int nitems, int* __restrict__ ctr, const T* __restrict__ wz,
     const T* __restrict__ wxp, const T* __restrict__ wyq,
@@ -1566,7 +1588,7 @@ static int spread_p(const DevParticles<T>& lex, long long N, const Geo& g,
     SE1P_CHECK_LAUNCH();
     dim3 grid((g.Mt1 + kSpreadTile - 1) / kSpreadTile,
               (g.Mt2 + kSpreadTile - 1) / kSpreadTile, g.M3 / CZ);
-    hipLaunchKernelGGL((spread_kernel<T, P>), grid, dim3(64), 0, s, wz, wxp,
+    hipLaunchKernelGGL((spread_kernel<T, P>), grid, dim3(64 * spread_waves(P)), 0, s, wz, wxp,
                        wyq, lex.cy, lex.start, Hpart, pstride, g, CZ, KP);
     SE1P_CHECK_LAUNCH();
     return 0;
@@ -1743,7 +1765,7 @@ static int batch_p(const BatchArgs<T>& a, const T* x, const T* q, T* phi,
                            dim3(128), 0, s, a.lex, N, a.sys_of, a.sys, a.wz,
                            a.wxp, a.wyq);
         hipLaunchKernelGGL((bspread_kernel<T, P>), dim3(L[kQSpread].grid),
-                           dim3(64), L[kQSpread].lds, s, a.sys, L[kQSpread].items,
+                           dim3(64 * spread_waves(P)), L[kQSpread].lds, s, a.sys, L[kQSpread].items,
                            L[kQSpread].nitems, a.qctr + kQSpread, a.wz, a.wxp,
                            a.wyq, a.lex.cy, a.lex.start);
         SE1P_CHECK_LAUNCH();
@@ -1805,7 +1827,7 @@ static int occ_p(int queue, size_t lds, int* bpc) {
     const void* f = nullptr;
     int bs = 256;
     switch (queue) {
-        case kQSpread: f = (const void*)bspread_kernel<T, P>; bs = 64; break;
+        case kQSpread: f = (const void*)bspread_kernel<T, P>; bs = 64 * spread_waves(P); break;
         case kQZfft: f = (const void*)bzfft_kernel<T>; break;
         case kQRowFwd: f = (const void*)browfwd_kernel<T>; break;
         case kQCols: f = (const void*)bcols_kernel<T>; break;
