@@ -857,7 +857,7 @@ __device__ __forceinline__ void gather_body(
             const bool zin = act && dzi >= 0 && dzi < P;
             const T dz = (tz - (T)(dzi + 1 - P / 2)) * h;
             const T wzv = zin ? dexp<T>(-a * dz * dz) : (T)0;
-            const T tz = dz * wzv;
+            const T tzw = dz * wzv;
             if (__any(zin)) {
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
@@ -906,7 +906,7 @@ __device__ __forceinline__ void gather_body(
                         phi = fma(wxz, sy, phi);
                         ey = fma(wxz, sty, ey);
                         ex = fma(ddx * wxz, sy, ex);
-                        ez = fma(wx * tz, sy, ez);
+                        ez = fma(wx * tzw, sy, ez);
                     }
                 }
             }
@@ -959,6 +959,37 @@ __global__ __launch_bounds__(64) void gather_kernel(
 // exponential: erfc(x) = exp(-x^2) erfcx(x) with erfcx from the fitted
 // polynomial of erfcx_poly.h (relative error 6e-12); FP32 does the same
 // with a degree-8 float fit (2e-7).
+// FP64 FMA in its three-operand form.  In polynomial loops the compiler
+// otherwise picks the two-address form and copies the loop-invariant
+// coefficient into the accumulator first, one extra move per step.
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// exp(y) for -708 < y <= 0: y = k ln2 + r with |r| <= ln2/2 (Cody-Waite
+// split of ln2), exp(r) by its Taylor series to degree 11 (truncation
+// below 7e-15 relative), scaled by 2^k.
+__device__ __forceinline__ double exp_neg(double y) {
+    const double k = rint(y * 1.4426950408889634074);
+    double r = fma3(-k, 6.93147180369123816490e-01, y);
+    r = fma3(-k, 1.90821492927058770002e-10, r);
+    double p = 1.0 / 39916800.0;                      // 1/11!
+    p = fma3(p, r, 1.0 / 3628800.0);
+    p = fma3(p, r, 1.0 / 362880.0);
+    p = fma3(p, r, 1.0 / 40320.0);
+    p = fma3(p, r, 1.0 / 5040.0);
+    p = fma3(p, r, 1.0 / 720.0);
+    p = fma3(p, r, 1.0 / 120.0);
+    p = fma3(p, r, 1.0 / 24.0);
+    p = fma3(p, r, 1.0 / 6.0);
+    p = fma3(p, r, 0.5);
+    p = fma3(p, r, 1.0);
+    p = fma3(p, r, 1.0);
+    return ldexp(p, (int)k);
+}
+
 template <typename T>
 __device__ __forceinline__ void pair_terms(T r2, T xi, T xi2, T c_erf, T qn,
                                            T& ec, T& f);
@@ -970,7 +1001,7 @@ __device__ __forceinline__ void pair_terms<double>(double r2, double xi,
     const double rinv = rsqrt(r2);
     const double r = r2 * rinv;
     const double x = fmin(xi * r, kErfcxXmax);
-    const double e = exp(-xi2 * r2);
+    const double e = exp_neg(-xi2 * r2);
     const double den = 1.0 + kErfcxA * x;
     double t = __builtin_amdgcn_rcp(den);
     t = t * (2.0 - den * t);
@@ -979,7 +1010,7 @@ __device__ __forceinline__ void pair_terms<double>(double r2, double xi,
     const double u = fma(t, cu, -1.0 - kErfcxTmin * cu);
     double pv = kErfcxC[kErfcxDeg];
 #pragma unroll
-    for (int k = kErfcxDeg - 1; k >= 0; --k) pv = fma(pv, u, kErfcxC[k]);
+    for (int k = kErfcxDeg - 1; k >= 0; --k) pv = fma3(pv, u, kErfcxC[k]);
     ec = e * (t * pv) * rinv;
     f = qn * (ec + c_erf * e) * (rinv * rinv);
 }
