@@ -132,6 +132,10 @@ typedef struct se1p_plan_info {
     int    precision;
     long long n_max;
     size_t workspace_bytes;
+    int    gather_block[3];  /* cells per gather block (x, y, z) */
+    int    gather_chunks;    /* 64-particle chunk slots per gather block */
+    int    spread_cz;        /* z cells per gridding chunk */
+    int    spread_kp;        /* partial grids written by gridding */
 } se1p_plan_info;
 
 typedef struct se1p_plan se1p_plan;

@@ -390,8 +390,15 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     add((void**)&pl.d_slabs, pl.slabs.size() * sizeof(SlabDesc));
     add(&pl.phiF, N * pl.es);
     add(&pl.EF, 3 * N * pl.es);
-    add(&pl.phiR, N * pl.es);
-    add(&pl.ER, 3 * N * pl.es);
+    // Real-space work units: 16-target chunks, each split into rs_parts
+    // parts so that the launch has several units per resident wave slot
+    // (1024 SIMDs x 4 waves) and the last round is short.
+    {
+        const long long nchunks = (N + 15) / 16;
+        pl.rs_parts = (int)std::min<long long>(8, std::max<long long>(1, (32768 + nchunks - 1) / nchunks));
+    }
+    add(&pl.phiR, (size_t)pl.rs_parts * N * pl.es);
+    add(&pl.ER, 3 * (size_t)pl.rs_parts * N * pl.es);
     pl.nblk_comb = (int)((N + 255) / 256);
     add((void**)&pl.partials, (size_t)pl.nblk_comb * 8);
     add((void**)&pl.flag, 256);
@@ -481,7 +488,7 @@ int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
         DevParticles<T> lex = particles<T>(pl, true);
         DevParticles<T> blk = particles<T>(pl, false);
         if ((rc = launch_realspace<T>(lex, blk, N, pl.g, pl.bg, pl.prm.xi, pl.prm.rc,
-                                      (T*)pl.phiR, (T*)pl.ER, pl.stream)))
+                                      pl.rs_parts, (T*)pl.phiR, (T*)pl.ER, pl.stream)))
             return rc;
         mask |= 16;
     } else {
@@ -491,7 +498,7 @@ int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
     const double self_c = 2.0 * pl.prm.xi / std::sqrt(kPi);
     const int nb = (int)((N + 255) / 256);
     rc = launch_combine<T>(N, (const T*)q, (const T*)pl.phiF, (const T*)pl.EF,
-                           (const T*)pl.phiR, (const T*)pl.ER, self_c, comp,
+                           (const T*)pl.phiR, (const T*)pl.ER, pl.rs_parts, self_c, comp,
                            (T*)phi, (T*)efield, pl.partials, nb, energy,
                            pl.stream);
     if (rc) return rc;
@@ -709,6 +716,12 @@ int se1p_plan_get_info(const se1p_plan* pl, se1p_plan_info* info) {
     info->precision = pl->prec;
     info->n_max = pl->n_max;
     info->workspace_bytes = pl->ws_bytes;
+    info->gather_block[0] = pl->bg.BX;
+    info->gather_block[1] = pl->bg.BY;
+    info->gather_block[2] = pl->bg.BZ;
+    info->gather_chunks = pl->bg.CH;
+    info->spread_cz = pl->CZ;
+    info->spread_kp = pl->KP;
     return SE1P_OK;
 }
 

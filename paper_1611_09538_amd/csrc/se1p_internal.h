@@ -107,16 +107,19 @@ int launch_gather(const T* Ht, const DevParticles<T>& blk, long long N,
                   const Geo& g, const BinGeo& bg, T scale, T* phi_out,
                   T* E_out, hipStream_t s);
 
+// nparts: the candidate rows of each 16-target chunk are split in nparts
+// parts run as separate waves; part k writes slice k of phi_out / E_out.
 template <typename T>
 int launch_realspace(const DevParticles<T>& lex, const DevParticles<T>& blk,
                      long long N, const Geo& g, const BinGeo& bg, double xi,
-                     double rc, T* phi_out, T* E_out, hipStream_t s);
+                     double rc, int nparts, T* phi_out, T* E_out, hipStream_t s);
 
+// Totals; the real-space input is the sum of its nparts slices.
 template <typename T>
 int launch_combine(long long N, const T* q_in, const T* phiF, const T* EF,
-                   const T* phiR, const T* ER, double self_c, unsigned flags,
-                   T* phi, T* E, double* partials, int nblk, double* energy,
-                   hipStream_t s);
+                   const T* phiR, const T* ER, int nparts, double self_c,
+                   unsigned flags, T* phi, T* E, double* partials, int nblk,
+                   double* energy, hipStream_t s);
 
 template <typename T>
 int launch_check(const T* x, const T* q, long long N, double L1, double L2,

@@ -1037,7 +1037,7 @@ template <typename T>
 __device__ __forceinline__ void realspace_body(
     const DevParticles<T>& blk, const DevParticles<T>& lx, const Geo& g,
     T xi, T rc, int R, T* __restrict__ phi_out, T* __restrict__ E_out,
-    int pbeg, int pend, int chunk) {
+    int pbeg, int pend, int chunk, int part, int nparts) {
     __shared__ T cx_[64], cy_[64], cz_[64], cq_[64];
     __shared__ int rows_s[64], rows_e[64], rows_h[64];
     const int lane = threadIdx.x;
@@ -1106,7 +1106,10 @@ __device__ __forceinline__ void realspace_body(
         // does not wait on one dependent load per row.
         const int xlo = max(0, bx0 - R), xhi = min(g.M1 - 1, bx1 + R);
         const int nxr = xhi - xlo + 1;
-        const int nrows = (bz1 - bz0 + 1 + 2 * R) * nxr;
+        // this part's share of the rows: [r0, r1)
+        const int nrows_all = (bz1 - bz0 + 1 + 2 * R) * nxr;
+        const int r0 = (int)((long long)nrows_all * part / nparts);
+        const int nrows = (int)((long long)nrows_all * (part + 1) / nparts);
         auto load_rows = [&](int base) {
             const int r = base + lane;
             int rs = 0, re = 0, rsh = 0;
@@ -1132,11 +1135,11 @@ __device__ __forceinline__ void realspace_body(
             rows_h[lane] = rsh;
             __syncthreads();
         };
-        int rbase = 0, rk = 0;         // uniform: first row of the LDS block, row in it
-        bool more = nrows > 0;
+        int rbase = r0, rk = 0;        // uniform: first row of the LDS block, row in it
+        bool more = nrows > r0;
         int s_cur = 0, e_cur = 0, h_cur = 0;
         if (more) {
-            load_rows(0);
+            load_rows(r0);
             s_cur = __builtin_amdgcn_readfirstlane(rows_s[0]);
             e_cur = __builtin_amdgcn_readfirstlane(rows_e[0]);
             h_cur = __builtin_amdgcn_readfirstlane(rows_h[0]);
@@ -1224,11 +1227,15 @@ __device__ __forceinline__ void realspace_body(
     }
 }
 
+// Block b: chunk b / nparts, part b % nparts of its candidate rows; part k
+// writes slice k of phi_out / E_out (N values / N x 3 each).
 template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void realspace_kernel(
     DevParticles<T> blk, DevParticles<T> lx, Geo g, int N, T xi, T rc, int R,
-    T* __restrict__ phi_out, T* __restrict__ E_out) {
-    realspace_body<T>(blk, lx, g, xi, rc, R, phi_out, E_out, 0, N, blockIdx.x);
+    int nparts, T* __restrict__ phi_out, T* __restrict__ E_out) {
+    const int chunk = blockIdx.x / nparts, part = blockIdx.x - chunk * nparts;
+    realspace_body<T>(blk, lx, g, xi, rc, R, phi_out + (long long)part * N,
+                      E_out + 3LL * part * N, 0, N, chunk, part, nparts);
 }
 
 // ------------------------------------------------------------------------
@@ -1242,9 +1249,9 @@ template <typename T>
 __device__ __forceinline__ void combine_body(
     long long p0, long long N, const T* __restrict__ q,
     const T* __restrict__ phiF, const T* __restrict__ EF,
-    const T* __restrict__ phiR, const T* __restrict__ ER, double self_c,
-    unsigned flags, T* __restrict__ phi, T* __restrict__ E,
-    double* __restrict__ partial, int blk) {
+    const T* __restrict__ phiR, const T* __restrict__ ER, int nparts,
+    long long pstr, double self_c, unsigned flags, T* __restrict__ phi,
+    T* __restrict__ E, double* __restrict__ partial, int blk) {
     __shared__ double red[kCombineThreads];
     const long long li = (long long)blk * kCombineThreads + threadIdx.x;
     const long long i = p0 + li;
@@ -1253,14 +1260,22 @@ __device__ __forceinline__ void combine_body(
         const T qi = q[i];
         T ph = 0;
         if (flags & 1u) ph += phiF[i];
-        if (flags & 2u) ph += phiR[i];
+        if (flags & 2u) {       // real-space partial sums, in part order
+            T r = phiR[i];
+            for (int k = 1; k < nparts; ++k) r += phiR[k * pstr + i];
+            ph += r;
+        }
         if (flags & 4u) ph += (T)(-self_c) * qi;
         if (phi) phi[i] = ph;
         if (E) {
             for (int d = 0; d < 3; ++d) {
                 T v = 0;
                 if (flags & 1u) v += EF[3 * i + d];
-                if (flags & 2u) v += ER[3 * i + d];
+                if (flags & 2u) {
+                    T r = ER[3 * i + d];
+                    for (int k = 1; k < nparts; ++k) r += ER[3 * (k * pstr + i) + d];
+                    v += r;
+                }
                 E[3 * i + d] = v;
             }
         }
@@ -1279,10 +1294,10 @@ template <typename T>
 __global__ __launch_bounds__(kCombineThreads) void combine_kernel(
     long long N, const T* __restrict__ q, const T* __restrict__ phiF,
     const T* __restrict__ EF, const T* __restrict__ phiR,
-    const T* __restrict__ ER, double self_c, unsigned flags,
+    const T* __restrict__ ER, int nparts, double self_c, unsigned flags,
     T* __restrict__ phi, T* __restrict__ E, double* __restrict__ partials) {
-    combine_body<T>(0, N, q, phiF, EF, phiR, ER, self_c, flags, phi, E,
-                    partials + blockIdx.x, blockIdx.x);
+    combine_body<T>(0, N, q, phiF, EF, phiR, ER, nparts, N, self_c, flags, phi,
+                    E, partials + blockIdx.x, blockIdx.x);
 }
 
 __device__ __forceinline__ void energy_body(const double* __restrict__ partials,
@@ -1519,7 +1534,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void br
         DevParticles<T> l = lx;
         l.start = lx.start + sd.cl0;
         realspace_body<T>(blk, l, g, (T)sd.xi, (T)sd.rc, sd.R, phi_out, E_out,
-                          (int)sd.p0, (int)(sd.p0 + sd.n), w.a);
+                          (int)sd.p0, (int)(sd.p0 + sd.n), w.a, 0, 1);
     }
 }
 
@@ -1537,8 +1552,8 @@ __global__ __launch_bounds__(kCombineThreads) void bcombine_kernel(
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const unsigned f = sd.rs ? flags : (flags & ~2u);
-        combine_body<T>(sd.p0, sd.n, q, phiF, EF, phiR, ER, sd.self_c, f, phi,
-                        E, partials + sd.e0 + w.a, w.a);
+        combine_body<T>(sd.p0, sd.n, q, phiF, EF, phiR, ER, 1, 0, sd.self_c, f,
+                        phi, E, partials + sd.e0 + w.a, w.a);
     }
 }
 
@@ -1718,24 +1733,24 @@ int launch_gather(const T* Ht, const DevParticles<T>& blk, long long N,
 template <typename T>
 int launch_realspace(const DevParticles<T>& lex, const DevParticles<T>& blk,
                      long long N, const Geo& g, const BinGeo& bg, double xi,
-                     double rc, T* phi_out, T* E_out, hipStream_t s) {
+                     double rc, int nparts, T* phi_out, T* E_out, hipStream_t s) {
     (void)bg;
     const int R = (int)ceil(rc / g.h);
-    const unsigned nb = (unsigned)((N + 15) / 16);   // chunks of 16 targets
+    const unsigned nb = (unsigned)((N + 15) / 16) * nparts;   // chunks of 16 targets
     hipLaunchKernelGGL(realspace_kernel<T>, dim3(nb), dim3(64), 0, s, blk, lex,
-                       g, (int)N, (T)xi, (T)rc, R, phi_out, E_out);
+                       g, (int)N, (T)xi, (T)rc, R, nparts, phi_out, E_out);
     SE1P_CHECK_LAUNCH();
     return 0;
 }
 
 template <typename T>
 int launch_combine(long long N, const T* q_in, const T* phiF, const T* EF,
-                   const T* phiR, const T* ER, double self_c, unsigned flags,
-                   T* phi, T* E, double* partials, int nblkc, double* energy,
-                   hipStream_t s) {
+                   const T* phiR, const T* ER, int nparts, double self_c,
+                   unsigned flags, T* phi, T* E, double* partials, int nblkc,
+                   double* energy, hipStream_t s) {
     hipLaunchKernelGGL(combine_kernel<T>, dim3(nblkc), dim3(kCombineThreads),
-                       0, s, N, q_in, phiF, EF, phiR, ER, self_c, flags, phi, E,
-                       partials);
+                       0, s, N, q_in, phiF, EF, phiR, ER, nparts, self_c, flags,
+                       phi, E, partials);
     SE1P_CHECK_LAUNCH();
     if (energy) {
         hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(256), 0, s,
@@ -1906,10 +1921,10 @@ int batch_occupancy(int queue, int P, size_t lds, int* blocks_per_cu) {
     template int launch_realspace<T>(const DevParticles<T>&,                   \
                                      const DevParticles<T>&, long long,         \
                                      const Geo&, const BinGeo&, double, double, \
-                                     T*, T*, hipStream_t);                      \
+                                     int, T*, T*, hipStream_t);                 \
     template int launch_combine<T>(long long, const T*, const T*, const T*,    \
-                                   const T*, const T*, double, unsigned, T*,    \
-                                   T*, double*, int, double*, hipStream_t);     \
+                                   const T*, const T*, int, double, unsigned,   \
+                                   T*, T*, double*, int, double*, hipStream_t); \
     template int launch_check<T>(const T*, const T*, long long, double, double, \
                                  int*, double*, hipStream_t);                   \
     template int launch_batch<T>(const BatchArgs<T>&, const T*, const T*, T*,  \

@@ -32,6 +32,7 @@ struct se1p_plan {
     int n0[2] = {0, 0}, nl[2] = {0, 0};
     int nslab = 0;
     int CZ = 0, KP = 0;
+    int rs_parts = 1;       // real-space parts per 16-target chunk
     std::vector<SlabDesc> slabs;
     FftDesc dz{};
     long long tw_elems = 0;

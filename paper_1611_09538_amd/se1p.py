@@ -82,6 +82,10 @@ class PlanInfo(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("n_max", ctypes.c_longlong),
         ("workspace_bytes", ctypes.c_size_t),
+        ("gather_block", ctypes.c_int * 3),
+        ("gather_chunks", ctypes.c_int),
+        ("spread_cz", ctypes.c_int),
+        ("spread_kp", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -89,7 +93,10 @@ class PlanInfo(ctypes.Structure):
                 "Mt": tuple(self.Mt), "M3": self.M3, "P": self.P,
                 "n0": tuple(self.n0), "nl": tuple(self.nl), "n_l": self.n_l,
                 "nslab": self.nslab, "precision": self.precision,
-                "n_max": self.n_max, "workspace_bytes": self.workspace_bytes}
+                "n_max": self.n_max, "workspace_bytes": self.workspace_bytes,
+                "gather_block": tuple(self.gather_block),
+                "gather_chunks": self.gather_chunks, "spread_cz": self.spread_cz,
+                "spread_kp": self.spread_kp}
 
 
 class CostModel(ctypes.Structure):

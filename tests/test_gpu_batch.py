@@ -3,6 +3,9 @@ queues), the autotuner's parameters, and the HIP-graph replay.
 
 * Every system of a batch must give what a plan of its own gives (the two
   share kernels; the packed binning keeps each system's particle order).
+  A single plan splits each chunk's real-space candidates into parts summed
+  afterwards, while the batch's persistent queue runs whole chunks, so the
+  two agree to rounding, not bitwise.
 * Graph replays must equal the eager sequence, replay after replay, with
   other device work and synchronisations between them.
 * The batched workload (64 systems, N log-uniform in [1e3, 5e4], L3 uniform
@@ -65,12 +68,13 @@ def test_batch_equals_single_plans(prec, tol, P):
         o0, o1 = batch.offsets[s], batch.offsets[s + 1]
         plan = se1p.Plan(params[s], n_max=counts[s])
         ps, Es, Us = plan.eval(x[o0:o1], q[o0:o1])
-        dphi = (phi[o0:o1] - ps).abs().max().item()
-        dE = (E[o0:o1] - Es).abs().max().item()
-        dU = abs(U[s].item() - Us.item())
-        _say(f"system {s}: N={counts[s]} M3={params[s].M3} max|dphi|={dphi:.3e} "
-             f"max|dE|={dE:.3e} |dU|={dU:.3e}")
-        assert dphi == 0.0 and dE == 0.0 and dU == 0.0
+        dphi = ((phi[o0:o1] - ps).norm() / ps.norm()).item()
+        dE = ((E[o0:o1] - Es).norm() / Es.norm()).item()
+        dU = abs(U[s].item() - Us.item()) / abs(Us.item())
+        _say(f"system {s}: N={counts[s]} M3={params[s].M3} rel-rms dphi={dphi:.3e} "
+             f"dE={dE:.3e} |dU|/U={dU:.3e}")
+        bar = 1e-13 if prec == "fp64" else 1e-6
+        assert dphi < bar and dE < bar and dU < 10 * bar
         plan.close()
     batch.close()
 
