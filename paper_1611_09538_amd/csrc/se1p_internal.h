@@ -12,7 +12,7 @@ constexpr int kMaxRad = 16;      // radix passes per FFT length
 constexpr int kSpreadTile = 8;   // spread tile: 8 x 8 (x, y) pencils, one per lane
 // Waves per spread tile, splitting its particles: worth it when a particle
 // brings enough work (P z-points per lane) to pay for the per-plane LDS sum.
-constexpr int spread_waves(int P) { return P >= 16 ? 4 : 1; }
+constexpr int spread_waves(int P) { return P >= 20 ? 8 : (P >= 16 ? 4 : 1); }
 constexpr int kPad = 7;          // zero padding on each side of the x/y spread weights
 constexpr int kZfftCols = 32;    // columns per block in the z transforms
 constexpr int kMaxP = 32;
