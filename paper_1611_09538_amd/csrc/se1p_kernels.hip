@@ -1102,14 +1102,17 @@ __device__ __forceinline__ void realspace_body(
         // Candidate rows: fixed z cell and x cell, the y cells of the row
         // clipped to the cut-off sphere around the chunk's cell box.  Rows
         // are set up 64 at a time by the lanes (bounds from the lex cell
-        // starts, image shift in periods) and walked from LDS, so the wave
-        // does not wait on one dependent load per row.
+        // starts, image shift in periods) with an exclusive scan of their
+        // lengths in LDS; each batch's lanes then find their candidate by a
+        // binary search of that scan, so a wave never walks rows one by one.
         const int xlo = max(0, bx0 - R), xhi = min(g.M1 - 1, bx1 + R);
         const int nxr = xhi - xlo + 1;
         // this part's share of the rows: [r0, r1)
         const int nrows_all = (bz1 - bz0 + 1 + 2 * R) * nxr;
         const int r0 = (int)((long long)nrows_all * part / nparts);
         const int nrows = (int)((long long)nrows_all * (part + 1) / nparts);
+        int gbase = r0;                // uniform: first row of the current group
+        int gtotal = 0, gdone = 0;     // uniform: candidates of the group, taken
         auto load_rows = [&](int base) {
             const int r = base + lane;
             int rs = 0, re = 0, rsh = 0;
@@ -1129,52 +1132,45 @@ __device__ __forceinline__ void realspace_body(
                     rsh = (czu - czw) / g.M3;
                 }
             }
+            const int len = re - rs;
+            int incl = len;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int v = __shfl_up(incl, d);
+                if (lane >= d) incl += v;
+            }
             __syncthreads();           // earlier rows no longer read
             rows_s[lane] = rs;
-            rows_e[lane] = re;
+            rows_e[lane] = incl - len; // exclusive prefix of the lengths
             rows_h[lane] = rsh;
             __syncthreads();
+            gtotal = __builtin_amdgcn_readfirstlane(__shfl(incl, 63));
+            gdone = 0;
         };
-        int rbase = r0, rk = 0;        // uniform: first row of the LDS block, row in it
-        bool more = nrows > r0;
-        int s_cur = 0, e_cur = 0, h_cur = 0;
-        if (more) {
-            load_rows(r0);
-            s_cur = __builtin_amdgcn_readfirstlane(rows_s[0]);
-            e_cur = __builtin_amdgcn_readfirstlane(rows_e[0]);
-            h_cur = __builtin_amdgcn_readfirstlane(rows_h[0]);
-        }
+        if (gbase < nrows) load_rows(gbase);
         // The next batch of up to 64 candidates: lane l takes candidate
         // cand (-1: none) of image shift csh periods.  Returns the count.
+        // A batch never spans two row groups.
         auto next_batch = [&](int& cand, int& csh) {
-            int fill = 0;
             cand = -1;
             csh = 0;
-            while (fill < 64 && more) {
-                if (s_cur >= e_cur) {
-                    if (++rk == 64) {
-                        rbase += 64;
-                        rk = 0;
-                        if (rbase < nrows) load_rows(rbase);
-                    }
-                    if (rbase + rk >= nrows) {
-                        more = false;
-                        break;
-                    }
-                    s_cur = __builtin_amdgcn_readfirstlane(rows_s[rk]);
-                    e_cur = __builtin_amdgcn_readfirstlane(rows_e[rk]);
-                    h_cur = __builtin_amdgcn_readfirstlane(rows_h[rk]);
-                    continue;
-                }
-                const int take = min(e_cur - s_cur, 64 - fill);
-                if (lane >= fill && lane < fill + take) {
-                    cand = s_cur + lane - fill;
-                    csh = h_cur;
-                }
-                fill += take;
-                s_cur += take;
+            while (gdone >= gtotal) {
+                gbase += 64;
+                if (gbase >= nrows) return 0;
+                load_rows(gbase);
             }
-            return fill;
+            const int n = min(64, gtotal - gdone);
+            if (lane < n) {
+                const int o = gdone + lane;
+                int k = 0;             // last row whose prefix is <= o
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1)
+                    if (rows_e[k + step] <= o) k += step;
+                cand = rows_s[k] + (o - rows_e[k]);
+                csh = rows_h[k];
+            }
+            gdone += n;
+            return n;
         };
         // Software pipeline: the loads of the next batch are in flight
         // while the current batch is processed from LDS.

@@ -59,8 +59,8 @@ CASES = {
     # xi large enough that the real-space pairs stay few at this density
     # (2.5e5 per unit volume); M3 follows xi at the 1e-5 Fourier bar.
     "fp32_1e6": dict(n=1_000_000, box=(2.0, 2.0, 1.0), charges="uniform",
-                     seed=4, M3=96, P=12, tol=1e-5, precision="fp32",
-                     xi=48.0, nl=8, sl=2.0, rc=0.069, pad_free=4),
+                     seed=4, M3=120, P=12, tol=1e-5, precision="fp32",
+                     xi=60.0, nl=10, sl=2.0, rc=0.055, pad_free=4),
 }
 
 
