@@ -17,6 +17,8 @@ Extra fields:
                   bounds (FP64 vector flops; LDS bytes for the gather)
   fp32            the N = 1e6 FP32 system (2 x 2 x 1, P = 12, rel-RMS 1e-5):
                   FP32 path and the FP64 path at the same parameters
+  adaptive_fft    the transform stage against the plain upsampled transform
+                  (every k3 slab upsampled) on the same system
   batched         64 systems (N log-uniform in [1e3, 5e4]) in one graph
                   launch, FP32 at 1e-5, against one plan per system (FP32 and
                   FP64) at the same parameters
@@ -41,16 +43,15 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1611_09538_amd", "csrc", "se1p_kernels.hip")
 
-# Flops per in-range pair of the real-space sum (phi and E), counting each
-# add, multiply and compare-free FMA half as one flop and rsqrt / exp / erfc
-# as one each:
+# Flops per in-range pair of the real-space sum (phi and E) as the kernel
+# formulates it, counting each add and multiply (an FMA as two) and rsqrt /
+# exp / reciprocal as one each:
 #   FP64: distance and r^2 8, rsqrt and r 2, exponent and exp 3,
 #         reciprocal with two Newton steps 9, Chebyshev variable 2,
-#         degree-16 Horner 32, erfc / r 2, phi update 2, radial factor 5,
-#         field update 6                                          = 71
-#   FP32: distance and r^2 8, rsqrt and r 2, erfc 1, exponent and exp 3,
-#         erfc / r 1, phi update 2, radial factor 5, field update 6 = 28
-PAIR_FLOPS = {"f64": 71.0, "f32": 28.0}
+#         degree-12 Horner 24, erfc / r 2, phi update 2, radial factor 5,
+#         field update 6                                          = 63
+#   FP32: the same with one reciprocal and a degree-8 Horner      = 47
+PAIR_FLOPS = {"f64": 63.0, "f32": 47.0}
 
 
 def parse():
@@ -61,7 +62,7 @@ def parse():
     ap.add_argument("--case", default="fp64_1e5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the FP32 and batched measurements")
+                    help="skip the adaptive-transform, FP32 and batched measurements")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calib", action="store_true",
@@ -157,6 +158,30 @@ def fp32_extra(se1p, workloads, torch, dev, steps, warmup):
         del xt, qt, phi, E, U
     out["speedup_fp32_over_fp64"] = out["f64"]["ms_per_step"] / out["f32"]["ms_per_step"]
     return out
+
+
+def adaptive_extra(se1p, workloads, torch, dev, steps, warmup, case, kspace_ms, phi_ad):
+    """The adaptive transform against the plain upsampled one (every k3 slab
+    upsampled by s_l, the k3 = 0 slab as before) on the same system."""
+    x, q, box, c = workloads.make_case(case)
+    N = x.shape[0]
+    prm = se1p.make_params(box, c["xi"], c["M3"], c["P"], c["M3"] // 2, c["sl"],
+                           rc=c["rc"], pad_free=c["pad_free"])
+    plan = se1p.Plan(prm, n_max=N)
+    xt = torch.tensor(x, device=dev)
+    qt = torch.tensor(q, device=dev)
+    phi = torch.empty(N, device=dev, dtype=torch.float64)
+    E = torch.empty((N, 3), device=dev, dtype=torch.float64)
+    U = torch.empty(1, device=dev, dtype=torch.float64)
+    plan.timing_enable(True)
+    timed(lambda: plan.eval_into(xt, qt, phi, E, U), steps, warmup, torch)
+    st, nc = plan.timing_read()
+    plan.close()
+    plain = st["kspace"] / max(nc, 1)
+    d = (phi - phi_ad).norm() / phi_ad.norm()
+    return {"adaptive_kspace_ms": kspace_ms, "plain_kspace_ms": plain,
+            "speedup": plain / kspace_ms, "n_l_plain": c["M3"] // 2,
+            "rel_rms_phi_adaptive_vs_plain": float(d.item())}
 
 
 def batched_extra(se1p, workloads, torch, dev, steps, warmup):
@@ -318,6 +343,10 @@ def main():
         del src, dst
 
     if not a.no_extras:
+        if prec == se1p.FP64:
+            out["adaptive_fft"] = adaptive_extra(se1p, workloads, torch, dev,
+                                                 max(5, a.steps // 2), 2, a.case,
+                                                 st_ms["kspace"], phi)
         out["fp32"] = fp32_extra(se1p, workloads, torch, dev, max(5, a.steps // 2), 2)
         print("fp32 done", file=sys.stderr, flush=True)
         out["batched"] = batched_extra(se1p, workloads, torch, dev, max(5, a.steps // 2), 2)

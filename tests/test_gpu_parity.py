@@ -251,3 +251,26 @@ def test_input_errors():
     with pytest.raises(se1p.SE1PError) as e:
         plan.eval(big, torch.zeros(17, device=dev, dtype=torch.float64))
     assert e.value.code == se1p.ERR_TOO_MANY
+
+
+def test_adaptive_transform_matches_plain_upsampled():
+    """Upsampling only the slabs 0 < |k3| <= 2 pi n_l / L3 (eq. upsamplings)
+    must reproduce the plain upsampled transform (every slab upsampled) to
+    the method's accuracy; the plain one is the reference of the adaptive
+    design (section 3.3)."""
+    dev = _dev()
+    se1p = _se1p()
+    x, q, box, c = workloads.make_case("small")
+    out = []
+    for nl in (c["nl"], c["M3"] // 2):
+        prm = se1p.make_params(box, c["xi"], c["M3"], c["P"], nl, c["sl"], rc=c["rc"],
+                               pad_free=c["pad_free"])
+        plan = se1p.Plan(prm, n_max=x.shape[0])
+        phi, E, _ = plan.eval(torch.tensor(x, device=dev), torch.tensor(q, device=dev),
+                              flags=se1p.KSPACE)
+        out.append((phi.cpu().numpy(), E.cpu().numpy()))
+    p_ref = oracle.ewald_total(x, q, box)[0]
+    dphi = np.linalg.norm(out[0][0] - out[1][0]) / np.linalg.norm(p_ref)
+    dE = np.linalg.norm(out[0][1] - out[1][1]) / np.linalg.norm(out[1][1])
+    print("adaptive vs plain upsampled: phi %.2e E %.2e" % (dphi, dE), flush=True)
+    assert dphi < 1e-9 and dE < 1e-8
