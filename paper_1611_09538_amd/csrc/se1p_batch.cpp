@@ -531,7 +531,10 @@ int se1p_batch_create(int nsys, const se1p_params* params,
     b->sys.resize(nsys);
     int rc = SE1P_OK;
     if (hipGetDevice(&b->device) != hipSuccess) rc = SE1P_ERR_HIP;
-    for (int s = 0; s < nsys && !rc; ++s) rc = plan_geometry(b->sys[s], params[s], counts[s]);
+    for (int s = 0; s < nsys && !rc; ++s) {
+        b->sys[s].in_batch = true;
+        rc = plan_geometry(b->sys[s], params[s], counts[s]);
+    }
     if (!rc) rc = b->prec == SE1P_FP64 ? build_batch<double>(*b) : build_batch<float>(*b);
     if (!rc && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
         b->cap = nullptr;

@@ -133,7 +133,10 @@ double poisson_chunks(double m) {
     return acc;
 }
 
-void choose_blocks(se1p_plan& pl) {
+// fill: apply the penalty for launches too small to fill the chip (a system
+// on its own); mt1, mt2 > 0: only blocks whose footprint fits an extended
+// grid of that size (nb * B + P <= Mt).
+void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
     // Each chunk stages BZ + P - 1 grid planes of (BX + P - 1) x (BY + P - 1)
     // values in LDS and every lane reads its own P x P window of each plane
     // its z support covers.  Blocks keep BX * BY <= 32 with BY even and the
@@ -158,6 +161,8 @@ void choose_blocks(se1p_plan& pl) {
             // the pitch holds whole chunks only if BY does
             if ((BY * (int)pl.es) % 16) continue;
             for (int BX = 1; BX * BY <= 32; ++BX) {
+                if (mt1 > 0 && ((pl.M1 + BX - 1) / BX) * BX + P > mt1) continue;
+                if (mt2 > 0 && ((pl.M2 + BY - 1) / BY) * BY + P > mt2) continue;
                 const double m = rho * BX * BY * BZ;
                 if (m > 64.0 && BX * BY * BZ > bymin) continue;
                 const double nblocks = (double)((pl.M1 + BX - 1) / BX) *
@@ -168,7 +173,7 @@ void choose_blocks(se1p_plan& pl) {
                                               planes * (BX + P - 1.0) * (BY + P - 1.0) / 16.0);
                 double cost = (work + 200.0) / std::max(m, 1e-6);
                 const double waves = nblocks * chunks;
-                if (waves < 2048.0) cost *= 2048.0 / std::max(waves, 1.0);
+                if (fill && waves < 2048.0) cost *= 2048.0 / std::max(waves, 1.0);
                 if (cost < best) {
                     best = cost; bx = BX; by = BY; bz = BZ;
                     ch = std::max(1, (int)std::ceil((m + 3.0 * std::sqrt(m) + 1.0) / 64.0));
@@ -207,7 +212,7 @@ void choose_spread(se1p_plan& pl) {
             if (ncz % k == 0) { KP = k; break; }
         if (KP < 0) continue;
         const double waves = (double)tiles * ncz * spread_waves(P);
-        const double fill = std::min(1.0, waves / 2048.0);
+        const double fill = pl.in_batch ? 1.0 : std::min(1.0, waves / 2048.0);
         const double score = fill * 4.0 - 0.05 * KP;
         if (score > bestScore) { bestScore = score; bestCZ = CZ; bestKP = KP; }
     }
@@ -251,13 +256,17 @@ int se1p::plan_geometry(se1p_plan& pl, const se1p_params& p, long long n_max) {
     if (pl.M2 < 1) pl.M2 = 1;
     g.M1 = pl.M1;
     g.M2 = pl.M2;
-    choose_blocks(pl);
-    // the gather stages planes of Ux x ldy values in 16-byte chunks that
-    // must not straddle LDS rows
-    if ((pl.bg.ldy * pl.es) % 16 != 0) return SE1P_ERR_UNSUPPORTED;
+    choose_blocks(pl, true, 0, 0);
     // Extended grid: M + P plus room for whole gather blocks, FFT-friendly.
     g.Mt1 = nice_size(std::max(pl.bg.nbx * pl.bg.BX + p.P, pl.M1 + p.P + p.pad_free));
     g.Mt2 = nice_size(std::max(pl.bg.nby * pl.bg.BY + p.P, pl.M2 + p.P + p.pad_free));
+    // A batch member keeps the grid (so the discretisation) of the system
+    // planned alone, and picks its gather blocks without the chip-fill
+    // penalty among those that fit that grid.
+    if (pl.in_batch) choose_blocks(pl, false, g.Mt1, g.Mt2);
+    // the gather stages planes of Ux x ldy values in 16-byte chunks that
+    // must not straddle LDS rows
+    if ((pl.bg.ldy * pl.es) % 16 != 0) return SE1P_ERR_UNSUPPORTED;
     g.ncol = (long long)g.Mt1 * g.Mt2;
     choose_spread(pl);
 

@@ -415,13 +415,29 @@ __device__ __forceinline__ void spread_body(
         }
     };
 
+    // Bounds of the tile's cell rows (one x cell, the y cells in range) for
+    // a z cell, one row per lane (at most kSpreadTile + P - 1 <= 64 rows),
+    // loaded for the next z cell while the current one is processed.
+    const int nr = (cxlo <= cxhi && cylo <= cyhi) ? cxhi - cxlo + 1 : 0;
+    auto load_rows = [&](int cz, int& rs, int& re) {
+        rs = re = 0;
+        if (lane < nr) {
+            const long long cb = ((long long)cz * g.M1 + cxlo + lane) * g.M2;
+            rs = cstart[cb + cylo];
+            re = cstart[cb + cyhi + 1];
+        }
+    };
+    int rsA, reA;
+    load_rows(cz0, rsA, reA);
+
     for (int ci = 0; ci < CZ; ++ci) {
-        const int cz = cz0 + ci;
-        if (cxlo <= cxhi && cylo <= cyhi) {
-            for (int cx = cxlo; cx <= cxhi; ++cx) {
-                const long long cb = ((long long)cz * g.M1 + cx) * g.M2;
-                const int s = cstart[cb + cylo];
-                const int e = cstart[cb + cyhi + 1];
+        int rsB = 0, reB = 0;
+        if (ci + 1 < CZ) load_rows(cz0 + ci + 1, rsB, reB);
+        {
+            for (int k = 0; k < nr; ++k) {
+                const int cx = cxlo + k;
+                const int s = __builtin_amdgcn_readlane(rsA, k);
+                const int e = __builtin_amdgcn_readlane(reA, k);
                 const int offx = lx - (cx + 1) + kPad;
                 int p = s + wv;
                 for (; p + W < e; p += 2 * W) {
@@ -447,6 +463,8 @@ __device__ __forceinline__ void spread_body(
                 }
             }
         }
+        rsA = rsB;
+        reA = reB;
         // plane zstart + ci is final
         finish(acc[0], zstart + ci);
 #pragma unroll

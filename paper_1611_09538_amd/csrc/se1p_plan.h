@@ -33,6 +33,8 @@ struct se1p_plan {
     int nslab = 0;
     int CZ = 0, KP = 0;
     int rs_parts = 1;       // real-space parts per 16-target chunk
+    bool in_batch = false;  // planned as a member of a batch: the batch, not
+                            // the system alone, fills the chip
     std::vector<SlabDesc> slabs;
     FftDesc dz{};
     long long tw_elems = 0;
