@@ -169,19 +169,22 @@ int build_batch(se1p_batch& b) {
         }
         lds[kQZfft] = std::max(lds[kQZfft], 2 * (kZfftCols / 2) * (size_t)(g.M3 + 1) * cs);
         lds[kQZifft] = lds[kQZfft];
-        const int nrb = (g.Mt1 + 3) / 4;
         for (int sl = 0; sl < pl.nslab; ++sl) {
             const SlabDesc& sd = pl.slabs[sl];
-            const double cr = 4.0 * sd.n2 * log2d(sd.n2);
-            for (int r = 0; r < nrb; ++r) {
-                it[kQRowFwd].push_back({cr, Item{s, r, sl, 0}});
-                it[kQRowInv].push_back({cr, Item{s, r, sl, 0}});
+            // rows / columns per item: about 1024 points per 256-thread
+            // item, at least 4 and at most 32 transforms
+            const int nrw = std::min(32, std::max(4, 1024 / sd.n2));
+            const int ncl = std::min(32, std::max(4, 1024 / (sd.n1 + 1)));
+            const double cr = (double)nrw * sd.n2 * log2d(sd.n2);
+            for (int r = 0; r < (g.Mt1 + nrw - 1) / nrw; ++r) {
+                it[kQRowFwd].push_back({cr, Item{s, r, sl, nrw}});
+                it[kQRowInv].push_back({cr, Item{s, r, sl, nrw}});
             }
-            const double cc = 8.0 * sd.n1 * log2d(sd.n1);
-            for (int c = 0; c < (sd.n2 + 3) / 4; ++c)
-                it[kQCols].push_back({cc, Item{s, c, sl, 0}});
-            lds[kQRowFwd] = std::max(lds[kQRowFwd], 2 * 4 * (size_t)sd.n2 * cs);
-            lds[kQCols] = std::max(lds[kQCols], 2 * 4 * (size_t)(sd.n1 + 1) * cs);
+            const double cc = 2.0 * ncl * sd.n1 * log2d(sd.n1);
+            for (int c = 0; c < (sd.n2 + ncl - 1) / ncl; ++c)
+                it[kQCols].push_back({cc, Item{s, c, sl, ncl}});
+            lds[kQRowFwd] = std::max(lds[kQRowFwd], 2 * (size_t)nrw * sd.n2 * cs);
+            lds[kQCols] = std::max(lds[kQCols], 2 * (size_t)ncl * (sd.n1 + 1) * cs);
         }
         lds[kQRowInv] = lds[kQRowFwd];
         const long long nblk = (long long)bg.nbx * bg.nby * bg.nbz;

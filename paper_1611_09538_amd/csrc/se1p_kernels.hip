@@ -620,15 +620,15 @@ template <typename T>
 __device__ __forceinline__ void rowfwd_body(
     const cplx<T>* __restrict__ Fz, cplx<T>* __restrict__ G,
     const SlabDesc* __restrict__ slabs, const Geo& g,
-    const cplx<T>* __restrict__ tw, int rb, int slab) {
+    const cplx<T>* __restrict__ tw, int rb, int slab, int nrb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SlabDesc& sd = slabs[slab];   // by reference: no private copy
     const int n2 = sd.n2;
-    const int x0 = rb * kRowsPerBlock;
+    const int x0 = rb * nrb;
     if (x0 >= g.Mt1) return;
-    const int nr = min(kRowsPerBlock, g.Mt1 - x0);
+    const int nr = min(nrb, g.Mt1 - x0);
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* B = A + kRowsPerBlock * n2;
+    cplx<T>* B = A + nrb * n2;
     const cplx<T>* src = Fz + (long long)slab * g.ncol;
     for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
         const int r = idx / n2, j = idx - r * n2;
@@ -651,7 +651,7 @@ __global__ __launch_bounds__(256) void rowfwd_kernel(
     const cplx<T>* __restrict__ Fz, cplx<T>* __restrict__ G,
     const SlabDesc* __restrict__ slabs, Geo g,
     const cplx<T>* __restrict__ tw) {
-    rowfwd_body<T>(Fz, G, slabs, g, tw, blockIdx.x, blockIdx.y);
+    rowfwd_body<T>(Fz, G, slabs, g, tw, blockIdx.x, blockIdx.y, kRowsPerBlock);
 }
 
 // Scaling factor (eq. scale_1p with G of eq. G_kappa_k), all constants and
@@ -679,43 +679,43 @@ __device__ __forceinline__ T slab_scale(const SlabDesc& sd, int kx, int ky,
 constexpr int kColsPerBlock = 4;
 
 // Fused column pass: zero-padded FFT along x, scaling, inverse FFT along x,
-// restriction to the first Mt1 rows, for kColsPerBlock columns ky.
+// restriction to the first Mt1 rows, for ncb columns ky.
 template <typename T>
 __device__ __forceinline__ void cols_body(
     cplx<T>* __restrict__ G, const SlabDesc* __restrict__ slabs, const Geo& g,
     const cplx<T>* __restrict__ tw, const T* __restrict__ S0, int cb,
-    int slab) {
+    int slab, int ncb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SlabDesc& sd = slabs[slab];   // by reference: no private copy
     const int n1 = sd.n1, n2 = sd.n2;
-    const int k0 = cb * kColsPerBlock;
+    const int k0 = cb * ncb;
     if (k0 >= n2) return;
-    const int nc = min(kColsPerBlock, n2 - k0);
+    const int nc = min(ncb, n2 - k0);
     const int stride = n1 + 1;
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* B = A + kColsPerBlock * stride;
+    cplx<T>* B = A + ncb * stride;
     cplx<T>* base = G + sd.off;
-    for (int idx = threadIdx.x; idx < n1 * kColsPerBlock; idx += blockDim.x) {
-        const int x = idx / kColsPerBlock, c = idx - x * kColsPerBlock;
+    for (int idx = threadIdx.x; idx < n1 * ncb; idx += blockDim.x) {
+        const int x = idx / ncb, c = idx - x * ncb;
         cplx<T> v;
         v.x = v.y = (T)0;
         if (x < g.Mt1 && c < nc) v = base[(long long)x * n2 + k0 + c];
         A[c * stride + x] = v;
     }
     __syncthreads();
-    cplx<T>* X = fft_lds<T>(A, B, kColsPerBlock, stride, sd.d1,
+    cplx<T>* X = fft_lds<T>(A, B, ncb, stride, sd.d1,
                             tw + sd.d1.twoff, -1);
     cplx<T>* Y = (X == A) ? B : A;
-    for (int idx = threadIdx.x; idx < n1 * kColsPerBlock; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < n1 * ncb; idx += blockDim.x) {
         const int c = idx / n1, kx = idx - c * n1;
         const T s = (c < nc) ? slab_scale<T>(sd, kx, k0 + c, g, S0) : (T)0;
         X[c * stride + kx] = cscale<T>(X[c * stride + kx], s);
     }
     __syncthreads();
-    cplx<T>* Z = fft_lds<T>(X, Y, kColsPerBlock, stride, sd.d1,
+    cplx<T>* Z = fft_lds<T>(X, Y, ncb, stride, sd.d1,
                             tw + sd.d1.twoff, +1);
-    for (int idx = threadIdx.x; idx < g.Mt1 * kColsPerBlock; idx += blockDim.x) {
-        const int x = idx / kColsPerBlock, c = idx - x * kColsPerBlock;
+    for (int idx = threadIdx.x; idx < g.Mt1 * ncb; idx += blockDim.x) {
+        const int x = idx / ncb, c = idx - x * ncb;
         if (c < nc) base[(long long)x * n2 + k0 + c] = Z[c * stride + x];
     }
 }
@@ -724,7 +724,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void cols_kernel(
     cplx<T>* __restrict__ G, const SlabDesc* __restrict__ slabs, Geo g,
     const cplx<T>* __restrict__ tw, const T* __restrict__ S0) {
-    cols_body<T>(G, slabs, g, tw, S0, blockIdx.x, blockIdx.y);
+    cols_body<T>(G, slabs, g, tw, S0, blockIdx.x, blockIdx.y, kColsPerBlock);
 }
 
 // Inverse FFT along y, restriction to the first Mt2 columns.
@@ -732,15 +732,15 @@ template <typename T>
 __device__ __forceinline__ void rowinv_body(
     const cplx<T>* __restrict__ G, cplx<T>* __restrict__ Fz,
     const SlabDesc* __restrict__ slabs, const Geo& g,
-    const cplx<T>* __restrict__ tw, int rb, int slab) {
+    const cplx<T>* __restrict__ tw, int rb, int slab, int nrb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SlabDesc& sd = slabs[slab];   // by reference: no private copy
     const int n2 = sd.n2;
-    const int x0 = rb * kRowsPerBlock;
+    const int x0 = rb * nrb;
     if (x0 >= g.Mt1) return;
-    const int nr = min(kRowsPerBlock, g.Mt1 - x0);
+    const int nr = min(nrb, g.Mt1 - x0);
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* B = A + kRowsPerBlock * n2;
+    cplx<T>* B = A + nrb * n2;
     const cplx<T>* src = G + sd.off;
     for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
         const int r = idx / n2, j = idx - r * n2;
@@ -760,7 +760,7 @@ __global__ __launch_bounds__(256) void rowinv_kernel(
     const cplx<T>* __restrict__ G, cplx<T>* __restrict__ Fz,
     const SlabDesc* __restrict__ slabs, Geo g,
     const cplx<T>* __restrict__ tw) {
-    rowinv_body<T>(G, Fz, slabs, g, tw, blockIdx.x, blockIdx.y);
+    rowinv_body<T>(G, Fz, slabs, g, tw, blockIdx.x, blockIdx.y, kRowsPerBlock);
 }
 
 // ------------------------------------------------------------------------
@@ -1470,7 +1470,7 @@ __global__ __launch_bounds__(256) void browfwd_kernel(
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
-        rowfwd_body<T>(sd.Fz, sd.G, sd.slabs, g, tw, w.a, w.b);
+        rowfwd_body<T>(sd.Fz, sd.G, sd.slabs, g, tw, w.a, w.b, w.c);
     }
 }
 
@@ -1484,7 +1484,7 @@ __global__ __launch_bounds__(256) void bcols_kernel(
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
-        cols_body<T>(sd.G, sd.slabs, g, tw, sd.S0, w.a, w.b);
+        cols_body<T>(sd.G, sd.slabs, g, tw, sd.S0, w.a, w.b, w.c);
     }
 }
 
@@ -1498,7 +1498,7 @@ __global__ __launch_bounds__(256) void browinv_kernel(
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
-        rowinv_body<T>(sd.G, sd.Fz, sd.slabs, g, tw, w.a, w.b);
+        rowinv_body<T>(sd.G, sd.Fz, sd.slabs, g, tw, w.a, w.b, w.c);
     }
 }
 
