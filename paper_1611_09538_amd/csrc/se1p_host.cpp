@@ -139,16 +139,21 @@ double poisson_chunks(double m) {
 void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
     // Each chunk stages BZ + P - 1 grid planes of (BX + P - 1) x (BY + P - 1)
     // values in LDS and every lane reads its own P x P window of each plane
-    // its z support covers.  Blocks keep BX * BY <= 32 with BY even and the
-    // LDS pitch == BY (mod 32), which spreads the lanes' window origins over
-    // distinct LDS banks.  Cost per particle: planes swept per chunk over the
-    // particles per chunk, with Poisson counts of mean m = rho * cells,
-    // penalised when the launch would not fill the chip.
+    // its z support covers.  The LDS serves 128 bytes per cycle from 32
+    // four-byte banks: 32 lanes per cycle for 4-byte words, 16 for 8-byte
+    // words.  With nb = 128 / word size, blocks keep BX * BY <= nb and the
+    // LDS pitch == BY (mod nb); the window origins of distinct (x, y) cells
+    // then fall in distinct banks, and lanes of one cell read the same
+    // address, so the window reads are free of bank conflicts.  Cost per
+    // particle: planes swept per chunk over the particles per chunk, with
+    // Poisson counts of mean m = rho * cells, penalised when the launch
+    // would not fill the chip.
     const double ncells = (double)pl.M1 * pl.M2 * pl.g.M3;
     const double rho = (double)std::max<long long>(pl.n_max, 1) / ncells;
     const int P = pl.g.P;
     double best = 1e300;
     const int bymin = std::max(2, 16 / (int)pl.es);   // whole 16-byte chunks
+    const int nbank = 128 / (int)pl.es;
     int bx = 1, by = bymin, bz = 1, ch = 1;
     const int bys[4] = {2, 4, 8, 16};
     const int bzs[4] = {1, 2, 4, 8};
@@ -160,7 +165,7 @@ void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
             // planes are staged in 16-byte chunks: with ldy == BY (mod 32)
             // the pitch holds whole chunks only if BY does
             if ((BY * (int)pl.es) % 16) continue;
-            for (int BX = 1; BX * BY <= 32; ++BX) {
+            for (int BX = 1; BX * BY <= nbank; ++BX) {
                 if (mt1 > 0 && ((pl.M1 + BX - 1) / BX) * BX + P > mt1) continue;
                 if (mt2 > 0 && ((pl.M2 + BY - 1) / BY) * BY + P > mt2) continue;
                 const double m = rho * BX * BY * BZ;
@@ -184,7 +189,7 @@ void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
     BinGeo& b = pl.bg;
     b.BX = bx; b.BY = by; b.BZ = bz; b.CH = ch;
     const int Uy = by + P - 1;
-    b.ldy = Uy + (((by - Uy) % 32) + 32) % 32;   // >= Uy, == BY (mod 32)
+    b.ldy = Uy + (((by - Uy) % nbank) + nbank) % nbank;   // >= Uy, == BY (mod nb)
     b.nbx = (pl.M1 + bx - 1) / bx;
     b.nby = (pl.M2 + by - 1) / by;
     b.nbz = pl.g.M3 / bz;

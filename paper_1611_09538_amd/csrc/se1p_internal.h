@@ -52,9 +52,10 @@ struct Geo {
 struct BinGeo {
     int BX, BY, BZ;
     int CH;               // gather waves per block (chunks of 64 particles)
-    int ldy;              // gather LDS row pitch: >= BY + P - 1, even, and
-                          // == BY (mod 32); with BX * BY <= 32 the lanes'
-                          // window origins then fall in distinct LDS banks
+    int ldy;              // gather LDS row pitch: >= BY + P - 1 and
+                          // == BY (mod nb), nb = 128 / word size; with
+                          // BX * BY <= nb the window origins of distinct
+                          // cells then fall in distinct LDS banks
     int nbx, nby, nbz;
     int cpb;              // cells per block
     long long ncell_lex;  // M3 * M1 * M2
