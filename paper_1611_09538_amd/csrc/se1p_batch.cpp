@@ -188,8 +188,9 @@ int build_batch(se1p_batch& b) {
         }
         lds[kQRowInv] = lds[kQRowFwd];
         const long long nblk = (long long)bg.nbx * bg.nby * bg.nbz;
-        const double m = rho * bg.cpb;
-        const double cg = (bg.BZ + P - 1.0) * P * P * std::max(1.0, m / (64.0 * bg.CH));
+        // a chunk spans about 64 / (rho * BX * BY) z cells of its block
+        const double span = std::min((double)bg.BZ, 64.0 / std::max(rho * bg.BX * bg.BY, 1e-12));
+        const double cg = (span + P - 1.0) * P * P;
         for (long long k = 0; k < nblk * bg.CH; ++k)
             it[kQGather].push_back({cg, Item{s, (int)k, 0, 0}});
         const int Ux = bg.BX + P - 1;

@@ -118,12 +118,13 @@ int check_params(const se1p_params& p) {
 }
 
 // Gather block shape: lanes are particles and every lane sweeps the union of
-// the supports of its chunk, so blocks should hold close to one wave of
-// particles while keeping the union small.  Expected cost per particle:
-//   E[chunks] * union / m, with Poisson counts of mean m = rho * cells,
-// penalised when the launch would not fill the chip.
+// the supports of its chunk (64 consecutive particles of a block), so a
+// chunk should be full while its z extent stays small.  Expected cost per
+// particle: E[chunks] * union / m, with Poisson counts of mean m = rho *
+// cells, penalised when the launch would not fill the chip.
 double poisson_chunks(double m) {
-    // E[ceil(k / 64)] for k ~ Poisson(m)
+    // E[ceil(k / 64)] for k ~ Poisson(m); for large m, m / 64 + 1/2
+    if (m > 400.0) return m / 64.0 + 0.5;
     double pk = std::exp(-m), acc = 0.0;
     const int kmax = (int)(m + 12.0 * std::sqrt(m + 1.0) + 80.0);
     for (int k = 0; k <= kmax; ++k) {
@@ -144,10 +145,13 @@ void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
     // words.  With nb = 128 / word size, blocks keep BX * BY <= nb and the
     // LDS pitch == BY (mod nb); the window origins of distinct (x, y) cells
     // then fall in distinct banks, and lanes of one cell read the same
-    // address, so the window reads are free of bank conflicts.  Cost per
-    // particle: planes swept per chunk over the particles per chunk, with
-    // Poisson counts of mean m = rho * cells, penalised when the launch
-    // would not fill the chip.
+    // address, so the window reads are free of bank conflicts.  Blocks may
+    // be tall in z (up to whole columns): particles are sorted by z inside a
+    // block, so a chunk of 64 spans about 64 / (rho * BX * BY) z cells and
+    // sweeps that many planes plus P - 1.  Cost per particle: planes swept
+    // per chunk times chunks over the particles per block, with Poisson
+    // counts of mean m = rho * cells, penalised when the launch has fewer
+    // waves than the chip has SIMDs.
     const double ncells = (double)pl.M1 * pl.M2 * pl.g.M3;
     const double rho = (double)std::max<long long>(pl.n_max, 1) / ncells;
     const int P = pl.g.P;
@@ -156,10 +160,12 @@ void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
     const int nbank = 128 / (int)pl.es;
     int bx = 1, by = bymin, bz = 1, ch = 1;
     const int bys[4] = {2, 4, 8, 16};
-    const int bzs[4] = {1, 2, 4, 8};
-    for (int iz = 0; iz < 4; ++iz) {
+    std::vector<int> bzs;
+    for (int z = 1; z < pl.g.M3; z *= 2)
+        if (pl.g.M3 % z == 0) bzs.push_back(z);
+    bzs.push_back(pl.g.M3);
+    for (size_t iz = 0; iz < bzs.size(); ++iz) {
         const int BZ = bzs[iz];
-        if (pl.g.M3 % BZ) continue;
         for (int iy = 0; iy < 4; ++iy) {
             const int BY = bys[iy];
             // planes are staged in 16-byte chunks: with ldy == BY (mod 32)
@@ -169,16 +175,16 @@ void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
                 if (mt1 > 0 && ((pl.M1 + BX - 1) / BX) * BX + P > mt1) continue;
                 if (mt2 > 0 && ((pl.M2 + BY - 1) / BY) * BY + P > mt2) continue;
                 const double m = rho * BX * BY * BZ;
-                if (m > 64.0 && BX * BY * BZ > bymin) continue;
                 const double nblocks = (double)((pl.M1 + BX - 1) / BX) *
                                        ((pl.M2 + BY - 1) / BY) * (pl.g.M3 / BZ);
                 const double chunks = std::max(poisson_chunks(m), 1e-9);
-                const double planes = BZ + P - 1.0;
+                const double span = std::min((double)BZ, 64.0 / (rho * BX * BY));
+                const double planes = span + P - 1.0;
                 const double work = chunks * (planes * P * P * 2.0 +
                                               planes * (BX + P - 1.0) * (BY + P - 1.0) / 16.0);
                 double cost = (work + 200.0) / std::max(m, 1e-6);
                 const double waves = nblocks * chunks;
-                if (fill && waves < 2048.0) cost *= 2048.0 / std::max(waves, 1.0);
+                if (fill && waves < 1024.0) cost *= 1024.0 / std::max(waves, 1.0);
                 if (cost < best) {
                     best = cost; bx = BX; by = BY; bz = BZ;
                     ch = std::max(1, (int)std::ceil((m + 3.0 * std::sqrt(m) + 1.0) / 64.0));

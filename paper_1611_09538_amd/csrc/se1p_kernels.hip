@@ -211,8 +211,11 @@ __device__ __forceinline__ void cell_of(T x, T y, T z, const Geo& g, T& zw,
 
 // Blocks of cells are numbered along a serpentine path (x reversed on odd
 // z planes, y reversed on odd rows), so consecutive blocks are always face
-// neighbours: a run of consecutive particles of the block order stays
-// spatially compact across block boundaries.
+// neighbours; inside a block the cells run z-major, with z reversed in odd
+// blocks, so that the last cells of a block and the first of the next one
+// share a z layer.  A run of consecutive particles of the block order thus
+// stays spatially compact across block boundaries, also for blocks that
+// are whole z columns.
 __device__ __forceinline__ int block_index(int bz, int bx, int by, const BinGeo& bg) {
     const int bxs = (bz & 1) ? bg.nbx - 1 - bx : bx;
     const int row = bz * bg.nbx + bxs;
@@ -241,7 +244,9 @@ __device__ __forceinline__ void cell_keys(const T* __restrict__ xin, long long i
     const int bz = cz / bg.BZ, iz = cz - bz * bg.BZ;
     const int bx = cx / bg.BX, ix = cx - bx * bg.BX;
     const int by = cy / bg.BY, iy = cy - by * bg.BY;
-    kb = block_index(bz, bx, by, bg) * bg.cpb + (iz * bg.BX + ix) * bg.BY + iy;
+    const int b = block_index(bz, bx, by, bg);
+    const int izs = (b & 1) ? bg.BZ - 1 - iz : iz;
+    kb = b * bg.cpb + (izs * bg.BX + ix) * bg.BY + iy;
 }
 
 template <typename T>
