@@ -881,7 +881,9 @@ __device__ __forceinline__ void gather_body(
             const T dz = (tz - (T)(dzi + 1 - P / 2)) * h;
             const T wzv = zin ? dexp<T>(-a * dz * dz) : (T)0;
             const T tzw = dz * wzv;
-            if (__any(zin)) {
+            // lanes are sorted by z, so at the first and last planes whole
+            // groups of lanes are idle and issue no LDS reads
+            if (zin) {
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
                     // y weights of this half of the window (registers)
