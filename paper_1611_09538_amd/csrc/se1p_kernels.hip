@@ -332,27 +332,43 @@ __global__ void bin_gather_kernel(const T* __restrict__ xin,
 // ------------------------------------------------------------------------
 // Per particle (lex order): z weights wz[P] (wave-uniform in the spread
 // kernel) and zero-padded x weights wxp[P + 2 kPad], q * y weights wyq.
+// One weight per thread, so that the stores are coalesced: elements
+// [0, N PW) are wxp, [N PW, 2 N PW) wyq and [2 N PW, 2 N PW + N P) wz.
 template <typename T, int P>
-__device__ __forceinline__ void spread_weights_one(const DevParticles<T>& lx,
-                                                   long long p, const Geo& g,
+constexpr long long spread_weight_count(long long N) {
+    return N * (2 * (P + 2 * kPad) + P);
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void spread_weight_elem(const DevParticles<T>& lx,
+                                                   long long N, long long i,
+                                                   const Geo& g,
                                                    T* __restrict__ wz,
                                                    T* __restrict__ wxp,
                                                    T* __restrict__ wyq) {
     constexpr int PW = P + 2 * kPad;
     const T h = (T)g.h, a = (T)g.alpha;
-    const T tx = lx.tx[p], ty = lx.ty[p], tz = lx.tz[p], q = lx.q[p];
-    // distance to grid point cx + 1 + u - P/2 (array index) in units of h
-    for (int k = 0; k < PW; ++k) {
-        const int u = k - kPad;
-        const bool in = (u >= 0) && (u < P);
-        const T dx = (tx - (T)(1 + u - P / 2)) * h;
-        const T dy = (ty - (T)(1 + u - P / 2)) * h;
-        wxp[p * PW + k] = in ? dexp<T>(-a * dx * dx) : (T)0;
-        wyq[p * PW + k] = in ? q * dexp<T>(-a * dy * dy) : (T)0;
-    }
-    for (int d = 0; d < P; ++d) {
-        const T dz = (tz - (T)(1 + d - P / 2)) * h;
-        wz[p * P + d] = dexp<T>(-a * dz * dz);
+    const long long nxy = N * PW;
+    if (i < 2 * nxy) {
+        const bool isy = i >= nxy;
+        const long long j = isy ? i - nxy : i;
+        const long long p = j / PW;
+        // distance to grid point cx + 1 + u - P/2 (array index) in units of h
+        const int u = (int)(j - p * PW) - kPad;
+        T w = 0;
+        if (u >= 0 && u < P) {
+            const T t = isy ? lx.ty[p] : lx.tx[p];
+            const T d = (t - (T)(1 + u - P / 2)) * h;
+            w = dexp<T>(-a * d * d);
+            if (isy) w = lx.q[p] * w;
+        }
+        (isy ? wyq : wxp)[j] = w;
+    } else {
+        const long long j = i - 2 * nxy;
+        const long long p = j / P;
+        const int d = (int)(j - p * P);
+        const T dz = (lx.tz[p] - (T)(1 + d - P / 2)) * h;
+        wz[j] = dexp<T>(-a * dz * dz);
     }
 }
 
@@ -360,9 +376,9 @@ template <typename T, int P>
 __global__ void spread_weights_kernel(DevParticles<T> lx, long long N, Geo g,
                                       T* __restrict__ wz, T* __restrict__ wxp,
                                       T* __restrict__ wyq) {
-    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N) return;
-    spread_weights_one<T, P>(lx, p, g, wz, wxp, wyq);
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= spread_weight_count<T, P>(N)) return;
+    spread_weight_elem<T, P>(lx, N, i, g, wz, wxp, wyq);
 }
 
 // A workgroup of spread_waves(P) waves owns the (x, y) pencils [X0, X0+8) x
@@ -1431,9 +1447,12 @@ __global__ void bspread_weights_kernel(DevParticles<T> lx, long long N,
                                        const SysDesc<T>* __restrict__ sys,
                                        T* __restrict__ wz, T* __restrict__ wxp,
                                        T* __restrict__ wyq) {
-    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N) return;
-    spread_weights_one<T, P>(lx, p, sys[sys_of[p]].g, wz, wxp, wyq);
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= spread_weight_count<T, P>(N)) return;
+    constexpr int PW = P + 2 * kPad;
+    const long long nxy = N * PW;
+    const long long p = i < 2 * nxy ? (i % nxy) / PW : (i - 2 * nxy) / P;
+    spread_weight_elem<T, P>(lx, N, i, sys[sys_of[p]].g, wz, wxp, wyq);
 }
 
 template <typename T, int P>
@@ -1650,8 +1669,9 @@ template <typename T, int P>
 static int spread_p(const DevParticles<T>& lex, long long N, const Geo& g,
                     int CZ, int KP, T* wz, T* wxp, T* wyq, T* Hpart,
                     long long pstride, hipStream_t s) {
-    hipLaunchKernelGGL((spread_weights_kernel<T, P>), dim3(nblk(N, 128)),
-                       dim3(128), 0, s, lex, N, g, wz, wxp, wyq);
+    hipLaunchKernelGGL((spread_weights_kernel<T, P>),
+                       dim3(nblk(spread_weight_count<T, P>(N), 256)), dim3(256), 0, s,
+                       lex, N, g, wz, wxp, wyq);
     SE1P_CHECK_LAUNCH();
     dim3 grid((g.Mt1 + kSpreadTile - 1) / kSpreadTile,
               (g.Mt2 + kSpreadTile - 1) / kSpreadTile, g.M3 / CZ);
@@ -1828,9 +1848,9 @@ static int batch_p(const BatchArgs<T>& a, const T* x, const T* q, T* phi,
     SE1P_CHECK_LAUNCH();
     const BatchLaunch* L = a.q;
     if (flags & 1u) {
-        hipLaunchKernelGGL((bspread_weights_kernel<T, P>), dim3(nblk(N, 128)),
-                           dim3(128), 0, s, a.lex, N, a.sys_of, a.sys, a.wz,
-                           a.wxp, a.wyq);
+        hipLaunchKernelGGL((bspread_weights_kernel<T, P>),
+                           dim3(nblk(spread_weight_count<T, P>(N), 256)), dim3(256), 0, s,
+                           a.lex, N, a.sys_of, a.sys, a.wz, a.wxp, a.wyq);
         hipLaunchKernelGGL((bspread_kernel<T, P>), dim3(L[kQSpread].grid),
                            dim3(64 * spread_waves(P)), L[kQSpread].lds, s, a.sys, L[kQSpread].items,
                            L[kQSpread].nitems, a.qctr + kQSpread, a.wz, a.wxp,
