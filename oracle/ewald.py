@@ -13,6 +13,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "se1p_oracle.c")
+_SRC3 = os.path.join(_HERE, "se3p_oracle.c")
 _LIB = os.path.join(_HERE, "libse1p_oracle.so")
 
 PARTS_REAL = 1
@@ -33,14 +34,20 @@ def lib_path() -> str:
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no -march so the object runs
     on any x86-64 host)."""
-    if force or not os.path.exists(_LIB) or (
-            os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
+    if force or _stale():
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
+               "-fno-fast-math", "-ffp-contract=off", _SRC, _SRC3, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def _stale() -> bool:
+    if not os.path.exists(_LIB):
+        return True
+    t = os.path.getmtime(_LIB)
+    return t < os.path.getmtime(_SRC) or t < os.path.getmtime(_SRC3)
 
 
 def _load():
@@ -48,8 +55,7 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(_LIB) or (
-                os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
+        if _stale():
             build(force=True)
         lib = ctypes.CDLL(_LIB)
         d = ctypes.c_double
@@ -72,6 +78,9 @@ def _load():
         lib.se1p_oracle_image_sum.restype = ctypes.c_int
         lib.se1p_oracle_image_sum.argtypes = [ctypes.c_long, p, p, d,
                                               ctypes.c_long, p]
+        lib.se3p_oracle_ewald.restype = ctypes.c_int
+        lib.se3p_oracle_ewald.argtypes = [ctypes.c_long, p, p, p, d, d,
+                                          ctypes.c_long, p, p]
         lib.se1p_oracle_init()
         _lib = lib
         return lib
@@ -177,3 +186,45 @@ def image_sum(x, q, L3, J):
     if rc != 0:
         raise RuntimeError("image_sum failed")
     return out
+
+
+def ewald3p(x, q, box, xi, rc=None, targets=None):
+    """Direct triply periodic Ewald sums at the targets (se3p_oracle.c).
+
+    Returns a dict of arrays over the targets:
+      phi_R, phi_F, phi_self  (ntarget,)
+      E_R, E_F                (ntarget, 3)
+    ``rc`` defaults to 6.5/xi, where erfc(xi rc) < 4e-20.
+    """
+    lib = _load()
+    x = _c(x, np.float64).reshape(-1, 3)
+    q = _c(q, np.float64).reshape(-1)
+    box = _c(box, np.float64).reshape(3)
+    N = x.shape[0]
+    if q.shape[0] != N:
+        raise ValueError("x and q sizes differ")
+    if rc is None:
+        rc = 6.5 / xi
+    if targets is None:
+        tg = None
+        nt = N
+    else:
+        tg = _c(targets, np.int64).reshape(-1)
+        nt = tg.shape[0]
+    out = np.zeros((nt, 9), dtype=np.float64)
+    rcode = lib.se3p_oracle_ewald(
+        N, x.ctypes.data, q.ctypes.data, box.ctypes.data, float(xi),
+        float(rc), nt, None if tg is None else tg.ctypes.data, out.ctypes.data)
+    if rcode != 0:
+        raise RuntimeError(f"oracle error {rcode}")
+    return {
+        "phi_R": out[:, 0].copy(), "phi_F": out[:, 1].copy(),
+        "phi_self": out[:, 2].copy(),
+        "E_R": out[:, 3:6].copy(), "E_F": out[:, 6:9].copy(),
+    }
+
+
+def ewald3p_total(x, q, box, xi, rc=None, targets=None):
+    """Total triply periodic potential and field at the targets."""
+    r = ewald3p(x, q, box, xi, rc=rc, targets=targets)
+    return r["phi_R"] + r["phi_F"] + r["phi_self"], r["E_R"] + r["E_F"]
