@@ -171,6 +171,24 @@ int se1p_suggest_params(double tol, const double box[3], long long N,
 int se1p_plan_create(const se1p_params* params, long long n_max,
                      void* stream, se1p_plan** out);
 
+/*
+ * se3p_plan_create -- the triply periodic counterpart (SE3P) the paper
+ * compares SE1P with in its example on efficiency against the triply
+ * periodic case: the same gridding, gather and real-space kernels, with the
+ * box periodic in x and y as well.  The gridded values are folded onto the
+ * periodic M1 x M2 x M3 grid, transformed without zero padding or
+ * upsampling, scaled by exp(-(1 - eta) k^2 / 4 xi^2) / k^2 for every k != 0
+ * (the k3 = 0 plane too, k = 0 dropped: tin-foil boundary), and the
+ * real-space sum takes sources from every periodic image within rc.
+ * Parameters as for se1p_plan_create; n_l, s_l and s0 are ignored; box[0]
+ * and box[1] must be multiples of h = box[2] / M3 (else SE1P_ERR_PARAM).
+ * The plan works with se1p_eval, se1p_plan_get_info, timing and
+ * se1p_plan_destroy; the stage calls se1p_spread, se1p_kspace_solve and
+ * se1p_gather return SE1P_ERR_UNSUPPORTED for it.
+ */
+int se3p_plan_create(const se1p_params* params, long long n_max,
+                     void* stream, se1p_plan** out);
+
 /* Releases the plan and its device workspace (synchronises its stream). */
 int se1p_plan_destroy(se1p_plan* plan);
 

@@ -281,6 +281,17 @@ int se1p::plan_geometry(se1p_plan& pl, const se1p_params& p, long long n_max) {
     g.ncol = (long long)g.Mt1 * g.Mt2;
     choose_spread(pl);
 
+    // Transform geometry.  SE3P transforms the periodic grid itself: the
+    // gridded values are folded onto M1 x M2 x M3 and every slab is a plain
+    // M1 x M2 transform, with Ghat = 1/k^2 for all k != 0.
+    pl.gf = g;
+    if (pl.periodic3) {
+        pl.gf.Mt1 = pl.M1;
+        pl.gf.Mt2 = pl.M2;
+        pl.gf.ncol = (long long)pl.M1 * pl.M2;
+    }
+    const Geo& gf = pl.gf;
+
     // k3 = 0 slab: R spans the support region; the padded period must hold
     // the support plus R (section 3.2; s0 >= 1 + sqrt 2 for a square).
     const double e1 = (pl.M1 + p.P) * g.h, e2 = (pl.M2 + p.P) * g.h;
@@ -292,6 +303,11 @@ int se1p::plan_geometry(se1p_plan& pl, const se1p_params& p, long long n_max) {
                                    pl.M2 + p.P + rcell, g.Mt2}));
     pl.nl[0] = nice_size(std::max((int)std::ceil(p.s_l * (pl.M1 + p.P) - 1e-9), g.Mt1));
     pl.nl[1] = nice_size(std::max((int)std::ceil(p.s_l * (pl.M2 + p.P) - 1e-9), g.Mt2));
+    if (pl.periodic3) {
+        pl.R = 0.0;
+        pl.n0[0] = pl.nl[0] = pl.M1;
+        pl.n0[1] = pl.nl[1] = pl.M2;
+    }
     if (std::max({pl.n0[0], pl.n0[1], pl.nl[0], pl.nl[1]}) > 4096)
         return SE1P_ERR_UNSUPPORTED;
 
@@ -316,10 +332,10 @@ int se1p::plan_geometry(se1p_plan& pl, const se1p_params& p, long long n_max) {
         sd.n3 = s;
         if (s == 0) { sd.n1 = pl.n0[0]; sd.n2 = pl.n0[1]; }
         else if (s <= p.n_l) { sd.n1 = pl.nl[0]; sd.n2 = pl.nl[1]; }
-        else { sd.n1 = g.Mt1; sd.n2 = g.Mt2; }
+        else { sd.n1 = gf.Mt1; sd.n2 = gf.Mt2; }
         sd.pad_ = 0;
         sd.off = off;
-        off += (long long)g.Mt1 * sd.n2;
+        off += (long long)gf.Mt1 * sd.n2;
         sd.pref = 4.0 * kPi * g.h * g.h * g.h * pl.cg * pl.cg /
                   ((double)p.M3 * sd.n1 * sd.n2);
         if (!factorize(sd.n1, sd.d1) || !factorize(sd.n2, sd.d2))
@@ -363,8 +379,11 @@ void se1p::plan_tables(const se1p_plan& pl, std::vector<double>& twd,
             const int fy = (ky <= b0 / 2) ? ky : ky - b0;
             const double k2 = 2.0 * kPi * fy / (b0 * g.h);
             const double kap2 = k1 * k1 + k2 * k2;
-            double v = z0.pref * std::exp(-(1.0 - g.eta) * kap2 / (4.0 * pl.prm.xi * pl.prm.xi)) *
-                       G_R(std::sqrt(kap2), pl.R);
+            // SE1P: truncated Green's function of the k3 = 0 mode; SE3P:
+            // the k3 = 0 plane of 1/k^2
+            const double gk = pl.periodic3 ? (kap2 > 0.0 ? 1.0 / kap2 : 0.0)
+                                           : G_R(std::sqrt(kap2), pl.R);
+            double v = z0.pref * std::exp(-(1.0 - g.eta) * kap2 / (4.0 * pl.prm.xi * pl.prm.xi)) * gk;
             if (kx == 0 && ky == 0) v = 0.0;   // (kappa, k3) = (0, 0)
             s0[(size_t)kx * b0 + ky] = v;
         }
@@ -402,7 +421,11 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     add(&pl.wyq, (size_t)N * PW * pl.es);
     pl.pstride = (long long)p.M3 * g.ncol;
     add(&pl.Hpart, (size_t)pl.KP * pl.pstride * pl.es);
-    add(&pl.Fz, (size_t)pl.nslab * g.ncol * cs);
+    add(&pl.Fz, (size_t)pl.nslab * pl.gf.ncol * cs);
+    if (pl.periodic3) {
+        add(&pl.Hper, (size_t)p.M3 * pl.gf.ncol * pl.es);
+        add(&pl.Htp, (size_t)p.M3 * pl.gf.ncol * pl.es);
+    }
     add(&pl.G, (size_t)pl.slab_elems * cs);
     add(&pl.Ht, (size_t)(pl.pstride + 64) * pl.es);   // rows are read in halves
     add(&pl.S0, (size_t)pl.n0[0] * pl.n0[1] * pl.es);
@@ -472,7 +495,8 @@ int run_spread(se1p_plan& pl, long long N) {
 template <typename T>
 int run_kspace(se1p_plan& pl, const T* Hin, int KP, T in_scale, T out_scale,
                T* Ht) {
-    return launch_kspace<T>(Hin, KP, pl.pstride, in_scale, pl.g, pl.nslab,
+    return launch_kspace<T>(Hin, KP, pl.periodic3 ? (long long)pl.g.M3 * pl.gf.ncol : pl.pstride,
+                            in_scale, pl.gf, pl.nslab,
                             pl.d_slabs, pl.slabs.data(), pl.dz,
                             (const cplx<T>*)pl.tw, (const T*)pl.S0,
                             (cplx<T>*)pl.Fz, (cplx<T>*)pl.G, out_scale, Ht,
@@ -492,7 +516,17 @@ int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
     if (comp & SE1P_KSPACE) {
         if ((rc = run_spread<T>(pl, N))) return rc;
         tmark(pl, 2);
-        if ((rc = run_kspace<T>(pl, (const T*)pl.Hpart, pl.KP, (T)1, (T)1, (T*)pl.Ht))) return rc;
+        if (pl.periodic3) {
+            // fold the gridded values onto the periodic grid, transform,
+            // and spread the result back over the gather's extended grid
+            if ((rc = launch_fold<T>((const T*)pl.Hpart, pl.KP, pl.pstride, pl.g, pl.gf,
+                                     (T*)pl.Hper, pl.stream))) return rc;
+            if ((rc = run_kspace<T>(pl, (const T*)pl.Hper, 1, (T)1, (T)1, (T*)pl.Htp))) return rc;
+            if ((rc = launch_unfold<T>((const T*)pl.Htp, pl.g, pl.gf, (T*)pl.Ht, pl.stream)))
+                return rc;
+        } else {
+            if ((rc = run_kspace<T>(pl, (const T*)pl.Hpart, pl.KP, (T)1, (T)1, (T*)pl.Ht))) return rc;
+        }
         tmark(pl, 3);
         DevParticles<T> blk = particles<T>(pl, false);
         if ((rc = launch_gather<T>((const T*)pl.Ht, blk, N, pl.g, pl.bg, (T)1,
@@ -508,7 +542,8 @@ int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
         DevParticles<T> lex = particles<T>(pl, true);
         DevParticles<T> blk = particles<T>(pl, false);
         if ((rc = launch_realspace<T>(lex, blk, N, pl.g, pl.bg, pl.prm.xi, pl.prm.rc,
-                                      pl.rs_parts, (T*)pl.phiR, (T*)pl.ER, pl.stream)))
+                                      pl.rs_parts, pl.periodic3, (T*)pl.phiR, (T*)pl.ER,
+                                      pl.stream)))
             return rc;
         mask |= 16;
     } else {
@@ -644,16 +679,27 @@ int se1p_suggest_params(double tol, const double box[3], long long N, double Q,
     return check_params(p);
 }
 
-int se1p_plan_create(const se1p_params* params, long long n_max, void* stream,
-                     se1p_plan** out) {
+namespace {
+int plan_create(const se1p_params* params, long long n_max, void* stream,
+                bool periodic3, se1p_plan** out) {
     if (!params || !out || n_max < 1 || n_max > (1LL << 30)) return SE1P_ERR_ARG;
     *out = nullptr;
     int rc = check_params(*params);
     if (rc) return rc;
+    if (periodic3) {
+        // the grid must tile each period exactly: L1 and L2 multiples of h
+        const double h = params->box[2] / params->M3;
+        for (int d = 0; d < 2; ++d) {
+            const double m = params->box[d] / h;
+            if (std::fabs(m - std::round(m)) > 1e-9 * m || std::round(m) < 2.0)
+                return SE1P_ERR_PARAM;
+        }
+    }
     se1p_plan* pl = new (std::nothrow) se1p_plan();
     if (!pl) return SE1P_ERR_NOMEM;
     if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return SE1P_ERR_HIP; }
     pl->stream = (hipStream_t)stream;
+    pl->periodic3 = periodic3;
     rc = build_plan(*pl, *params, n_max);
     if (rc) {
         if (pl->base) (void)hipFree(pl->base);
@@ -662,6 +708,17 @@ int se1p_plan_create(const se1p_params* params, long long n_max, void* stream,
     }
     *out = pl;
     return SE1P_OK;
+}
+}  // namespace
+
+int se1p_plan_create(const se1p_params* params, long long n_max, void* stream,
+                     se1p_plan** out) {
+    return plan_create(params, n_max, stream, false, out);
+}
+
+int se3p_plan_create(const se1p_params* params, long long n_max, void* stream,
+                     se1p_plan** out) {
+    return plan_create(params, n_max, stream, true, out);
 }
 
 int se1p_timing_enable(se1p_plan* pl, int enable) {
@@ -774,6 +831,7 @@ int se1p_eval(se1p_plan* pl, long long N, const void* x, const void* q,
 int se1p_spread(se1p_plan* pl, long long N, const void* x, const void* q,
                 void* grid) {
     if (!pl || !x || !q || !grid) return SE1P_ERR_ARG;
+    if (pl->periodic3) return SE1P_ERR_UNSUPPORTED;
     if (N < 1) return SE1P_ERR_ARG;
     if (N > pl->n_max) return SE1P_ERR_TOO_MANY;
     if (set_device(pl)) return SE1P_ERR_HIP;
@@ -793,6 +851,7 @@ int se1p_spread(se1p_plan* pl, long long N, const void* x, const void* q,
 
 int se1p_kspace_solve(se1p_plan* pl, const void* grid_in, void* grid_out) {
     if (!pl || !grid_in || !grid_out) return SE1P_ERR_ARG;
+    if (pl->periodic3) return SE1P_ERR_UNSUPPORTED;
     if (set_device(pl)) return SE1P_ERR_HIP;
     const double h3 = pl->g.h * pl->g.h * pl->g.h;
     const double in_s = 1.0 / pl->cg;
@@ -807,6 +866,7 @@ int se1p_kspace_solve(se1p_plan* pl, const void* grid_in, void* grid_out) {
 int se1p_gather(se1p_plan* pl, long long N, const void* x, const void* grid,
                 void* phi, void* efield) {
     if (!pl || !x || !grid) return SE1P_ERR_ARG;
+    if (pl->periodic3) return SE1P_ERR_UNSUPPORTED;
     if (N < 1) return SE1P_ERR_ARG;
     if (N > pl->n_max) return SE1P_ERR_TOO_MANY;
     if (set_device(pl)) return SE1P_ERR_HIP;

@@ -110,10 +110,21 @@ int launch_gather(const T* Ht, const DevParticles<T>& blk, long long N,
 
 // nparts: the candidate rows of each 16-target chunk are split in nparts
 // parts run as separate waves; part k writes slice k of phi_out / E_out.
+// periodic3: sources from the images in x and y as well (SE3P).
 template <typename T>
 int launch_realspace(const DevParticles<T>& lex, const DevParticles<T>& blk,
                      long long N, const Geo& g, const BinGeo& bg, double xi,
-                     double rc, int nparts, T* phi_out, T* E_out, hipStream_t s);
+                     double rc, int nparts, bool periodic3, T* phi_out, T* E_out,
+                     hipStream_t s);
+
+// SE3P: sum the KP partial extended grids (geometry g) onto the periodic
+// grid (geometry gf, Mt = M), and copy the periodic grid back out over the
+// extended grid for the gather.
+template <typename T>
+int launch_fold(const T* Hpart, int KP, long long pstride, const Geo& g,
+                const Geo& gf, T* Hper, hipStream_t s);
+template <typename T>
+int launch_unfold(const T* Htp, const Geo& g, const Geo& gf, T* Ht, hipStream_t s);
 
 // Totals; the real-space input is the sum of its nparts slices.
 template <typename T>

@@ -1074,7 +1074,9 @@ __device__ __forceinline__ void pair_terms<float>(float r2, float xi,
     f = qn * (ec + c_erf * e) * (rinv * rinv);
 }
 
-template <typename T>
+// PXY: x and y periodic too (SE3P); sources are taken from every image
+// within the cut-off.
+template <typename T, bool PXY = false>
 __device__ __forceinline__ void realspace_body(
     const DevParticles<T>& blk, const DevParticles<T>& lx, const Geo& g,
     T xi, T rc, int R, T* __restrict__ phi_out, T* __restrict__ E_out,
@@ -1088,6 +1090,8 @@ __device__ __forceinline__ void realspace_body(
     const T c_erf = (T)1.1283791670955125738961589031215 * xi;  // 2 xi / sqrt(pi)
     const T xi2 = xi * xi;
     const T L3 = (T)g.L3;
+    const T L1 = (T)(g.M1 * g.h), L2 = (T)(g.M2 * g.h);
+    (void)L1; (void)L2;
     const double rcell2 = (double)rc * (double)rc / (g.h * g.h);
 
     // one chunk of 16 consecutive targets of the block order; four lanes
@@ -1146,10 +1150,14 @@ __device__ __forceinline__ void realspace_body(
         // starts, image shift in periods) with an exclusive scan of their
         // lengths in LDS; each batch's lanes then find their candidate by a
         // binary search of that scan, so a wave never walks rows one by one.
-        const int xlo = max(0, bx0 - R), xhi = min(g.M1 - 1, bx1 + R);
+        // (PXY: x cells unclipped, wrapped with an image shift, and the y
+        // range split into one row per period it touches, NYP at most)
+        const int xlo = PXY ? bx0 - R : max(0, bx0 - R);
+        const int xhi = PXY ? bx1 + R : min(g.M1 - 1, bx1 + R);
         const int nxr = xhi - xlo + 1;
+        const int NYP = PXY ? (by1 - by0 + 2 * R) / g.M2 + 2 : 1;
         // this part's share of the rows: [r0, r1)
-        const int nrows_all = (bz1 - bz0 + 1 + 2 * R) * nxr;
+        const int nrows_all = (bz1 - bz0 + 1 + 2 * R) * nxr * NYP;
         const int r0 = (int)((long long)nrows_all * part / nparts);
         const int nrows = (int)((long long)nrows_all * (part + 1) / nparts);
         int gbase = r0;                // uniform: first row of the current group
@@ -1158,19 +1166,37 @@ __device__ __forceinline__ void realspace_body(
             const int r = base + lane;
             int rs = 0, re = 0, rsh = 0;
             if (r < nrows) {
-                const int czu = bz0 - R + r / nxr;
-                const int cxn = xlo + r % nxr;
+                const int rz = PXY ? r / NYP : r;
+                const int czu = bz0 - R + rz / nxr;
+                const int cxu = xlo + rz % nxr;
                 const int gz = max(0, max(bz0 - czu, czu - bz1) - 1);
-                const int gx = max(0, max(bx0 - cxn, cxn - bx1) - 1);
+                const int gx = max(0, max(bx0 - cxu, cxu - bx1) - 1);
                 const double rem = rcell2 - (double)gz * gz - (double)gx * gx;
                 if (rem >= 0.0) {
                     const int gy = (int)sqrt(rem) + 1;
-                    const int ylo = max(0, by0 - gy), yhi = min(g.M2 - 1, by1 + gy);
                     const int czw = imod(czu, g.M3);
-                    const long long cb = ((long long)czw * g.M1 + cxn) * g.M2;
-                    rs = lx.start[cb + ylo];
-                    re = lx.start[cb + yhi + 1];
-                    rsh = (czu - czw) / g.M3;
+                    if constexpr (PXY) {
+                        const int cxn = imod(cxu, g.M1);
+                        const int ylu = by0 - gy, yhu = by1 + gy;
+                        const int k = (ylu - imod(ylu, g.M2)) / g.M2 + r % NYP;   // period
+                        const int ya = max(ylu, k * g.M2) - k * g.M2;
+                        const int yb = min(yhu, k * g.M2 + g.M2 - 1) - k * g.M2;
+                        if (ya <= yb) {
+                            const long long cb = ((long long)czw * g.M1 + cxn) * g.M2;
+                            rs = lx.start[cb + ya];
+                            re = lx.start[cb + yb + 1];
+                            // image shifts in periods, 10 bits each
+                            rsh = (((cxu - cxn) / g.M1 + 512) << 20) | ((k + 512) << 10) |
+                                  ((czu - czw) / g.M3 + 512);
+                        }
+                    } else {
+                        const int cxn = cxu;
+                        const int ylo = max(0, by0 - gy), yhi = min(g.M2 - 1, by1 + gy);
+                        const long long cb = ((long long)czw * g.M1 + cxn) * g.M2;
+                        rs = lx.start[cb + ylo];
+                        re = lx.start[cb + yhi + 1];
+                        rsh = (czu - czw) / g.M3;
+                    }
                 }
             }
             const int len = re - rs;
@@ -1217,11 +1243,21 @@ __device__ __forceinline__ void realspace_body(
         // while the current batch is processed from LDS.
         int cand, csh;
         int nA = next_batch(cand, csh);
+        // source position of candidate c in the image of packed shift sh
+        auto src = [&](int c, int sh, T& px, T& py, T& pz) {
+            if constexpr (PXY) {
+                px = lx.x[c] + (T)((sh >> 20) - 512) * L1;
+                py = lx.y[c] + (T)(((sh >> 10) & 1023) - 512) * L2;
+                pz = lx.z[c] + (T)((sh & 1023) - 512) * L3;
+            } else {
+                px = lx.x[c];
+                py = lx.y[c];
+                pz = lx.z[c] + (T)sh * L3;
+            }
+        };
         T ax = 0, ay = 0, az = 0, aq = 0;
         if (cand >= 0) {
-            ax = lx.x[cand];
-            ay = lx.y[cand];
-            az = lx.z[cand] + (T)csh * L3;
+            src(cand, csh, ax, ay, az);
             aq = lx.q[cand];
         }
         while (nA > 0) {
@@ -1234,9 +1270,7 @@ __device__ __forceinline__ void realspace_body(
             const int nB = next_batch(cand, csh);
             T bx_ = 0, by_ = 0, bz_ = 0, bq_ = 0;
             if (cand >= 0) {
-                bx_ = lx.x[cand];
-                by_ = lx.y[cand];
-                bz_ = lx.z[cand] + (T)csh * L3;
+                src(cand, csh, bx_, by_, bz_);
                 bq_ = lx.q[cand];
             }
             process(nA);
@@ -1266,13 +1300,13 @@ __device__ __forceinline__ void realspace_body(
 
 // Block b: chunk b / nparts, part b % nparts of its candidate rows; part k
 // writes slice k of phi_out / E_out (N values / N x 3 each).
-template <typename T>
+template <typename T, bool PXY>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void realspace_kernel(
     DevParticles<T> blk, DevParticles<T> lx, Geo g, int N, T xi, T rc, int R,
     int nparts, T* __restrict__ phi_out, T* __restrict__ E_out) {
     const int chunk = blockIdx.x / nparts, part = blockIdx.x - chunk * nparts;
-    realspace_body<T>(blk, lx, g, xi, rc, R, phi_out + (long long)part * N,
-                      E_out + 3LL * part * N, 0, N, chunk, part, nparts);
+    realspace_body<T, PXY>(blk, lx, g, xi, rc, R, phi_out + (long long)part * N,
+                           E_out + 3LL * part * N, 0, N, chunk, part, nparts);
 }
 
 // ------------------------------------------------------------------------
@@ -1774,12 +1808,75 @@ int launch_gather(const T* Ht, const DevParticles<T>& blk, long long N,
 template <typename T>
 int launch_realspace(const DevParticles<T>& lex, const DevParticles<T>& blk,
                      long long N, const Geo& g, const BinGeo& bg, double xi,
-                     double rc, int nparts, T* phi_out, T* E_out, hipStream_t s) {
+                     double rc, int nparts, bool periodic3, T* phi_out, T* E_out,
+                     hipStream_t s) {
     (void)bg;
     const int R = (int)ceil(rc / g.h);
     const unsigned nb = (unsigned)((N + 15) / 16) * nparts;   // chunks of 16 targets
-    hipLaunchKernelGGL(realspace_kernel<T>, dim3(nb), dim3(64), 0, s, blk, lex,
-                       g, (int)N, (T)xi, (T)rc, R, nparts, phi_out, E_out);
+    if (periodic3) {
+        // image shifts are packed in 10 bits per direction
+        if (R + 2 > 200 * std::min(std::min(g.M1, g.M2), g.M3)) return -8;
+        hipLaunchKernelGGL((realspace_kernel<T, true>), dim3(nb), dim3(64), 0, s, blk, lex,
+                           g, (int)N, (T)xi, (T)rc, R, nparts, phi_out, E_out);
+    } else {
+        hipLaunchKernelGGL((realspace_kernel<T, false>), dim3(nb), dim3(64), 0, s, blk, lex,
+                           g, (int)N, (T)xi, (T)rc, R, nparts, phi_out, E_out);
+    }
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+// ------------------------------------------------------------------------
+// SE3P: periodic grid <-> extended grid
+// ------------------------------------------------------------------------
+// Array index a of the extended grid (Mt1 x Mt2, gridding and gather) holds
+// grid point a - P/2 of the period; the periodic grid gf (M1 x M2) sums
+// every extended point of its class mod (M1, M2) over the KP partial grids.
+template <typename T>
+__global__ void fold_kernel(const T* __restrict__ Hp, int KP, long long pstride,
+                            Geo g, Geo gf, T* __restrict__ Hper) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)g.M3 * gf.ncol) return;
+    const int y = (int)(i % gf.Mt2);
+    const long long r = i / gf.Mt2;
+    const int x = (int)(r % gf.Mt1);
+    const int z = (int)(r / gf.Mt1);
+    const int a0 = imod(x + g.P / 2, gf.Mt1), b0 = imod(y + g.P / 2, gf.Mt2);
+    T v = 0;
+    for (int k = 0; k < KP; ++k)
+        for (int a = a0; a < g.Mt1; a += gf.Mt1)
+            for (int b = b0; b < g.Mt2; b += gf.Mt2)
+                v += Hp[k * pstride + (long long)z * g.ncol + (long long)a * g.Mt2 + b];
+    Hper[i] = v;
+}
+
+template <typename T>
+__global__ void unfold_kernel(const T* __restrict__ Htp, Geo g, Geo gf,
+                              T* __restrict__ Ht) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)g.M3 * g.ncol) return;
+    const int b = (int)(i % g.Mt2);
+    const long long r = i / g.Mt2;
+    const int a = (int)(r % g.Mt1);
+    const int z = (int)(r / g.Mt1);
+    Ht[i] = Htp[(long long)z * gf.ncol + (long long)imod(a - g.P / 2, gf.Mt1) * gf.Mt2 +
+                imod(b - g.P / 2, gf.Mt2)];
+}
+
+template <typename T>
+int launch_fold(const T* Hpart, int KP, long long pstride, const Geo& g,
+                const Geo& gf, T* Hper, hipStream_t s) {
+    const long long n = (long long)g.M3 * gf.ncol;
+    hipLaunchKernelGGL(fold_kernel<T>, dim3(nblk(n, 256)), dim3(256), 0, s, Hpart, KP,
+                       pstride, g, gf, Hper);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+template <typename T>
+int launch_unfold(const T* Htp, const Geo& g, const Geo& gf, T* Ht, hipStream_t s) {
+    const long long n = (long long)g.M3 * g.ncol;
+    hipLaunchKernelGGL(unfold_kernel<T>, dim3(nblk(n, 256)), dim3(256), 0, s, Htp, g, gf, Ht);
     SE1P_CHECK_LAUNCH();
     return 0;
 }
@@ -1962,7 +2059,11 @@ int batch_occupancy(int queue, int P, size_t lds, int* blocks_per_cu) {
     template int launch_realspace<T>(const DevParticles<T>&,                   \
                                      const DevParticles<T>&, long long,         \
                                      const Geo&, const BinGeo&, double, double, \
-                                     int, T*, T*, hipStream_t);                 \
+                                     int, bool, T*, T*, hipStream_t);           \
+    template int launch_fold<T>(const T*, int, long long, const Geo&,          \
+                                const Geo&, T*, hipStream_t);                   \
+    template int launch_unfold<T>(const T*, const Geo&, const Geo&, T*,        \
+                                  hipStream_t);                                 \
     template int launch_combine<T>(long long, const T*, const T*, const T*,    \
                                    const T*, const T*, int, double, unsigned,   \
                                    T*, T*, double*, int, double*, hipStream_t); \

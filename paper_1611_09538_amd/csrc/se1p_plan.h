@@ -24,7 +24,10 @@ struct se1p_plan {
     int device = 0;
     hipStream_t stream = nullptr;
 
-    Geo g{};
+    Geo g{};                // gridding / gather geometry (extended grid)
+    Geo gf{};               // transform geometry: g itself for SE1P; the
+                            // periodic M1 x M2 x M3 grid for SE3P
+    bool periodic3 = false; // triply periodic (SE3P) plan
     BinGeo bg{};
     double cg = 0.0;        // (2 xi^2 / (pi eta))^{3/2}
     double R = 0.0;
@@ -53,6 +56,7 @@ struct se1p_plan {
     void *wz = nullptr, *wxp = nullptr, *wyq = nullptr;
     void* Hpart = nullptr;
     long long pstride = 0;
+    void *Hper = nullptr, *Htp = nullptr;   // SE3P: folded grid, transform output
     void* Fz = nullptr;
     void* G = nullptr;
     void* Ht = nullptr;

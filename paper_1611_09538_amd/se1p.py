@@ -136,6 +136,7 @@ EXPORTS = [
     "se1p_timing_enable", "se1p_timing_read", "se1p_calibrate",
     "se1p_autotune", "se1p_batch_create", "se1p_batch_destroy",
     "se1p_batch_eval", "se1p_batch_get_info", "se1p_batch_system_info",
+    "se3p_plan_create",
 ]
 
 NSTAGE = 6
@@ -163,6 +164,8 @@ def _lib():
                                         ctypes.POINTER(Params)]
     lib.se1p_plan_create.restype = i
     lib.se1p_plan_create.argtypes = [ctypes.POINTER(Params), ll, vp, ctypes.POINTER(vp)]
+    lib.se3p_plan_create.restype = i
+    lib.se3p_plan_create.argtypes = [ctypes.POINTER(Params), ll, vp, ctypes.POINTER(vp)]
     lib.se1p_plan_destroy.restype = i
     lib.se1p_plan_destroy.argtypes = [vp]
     lib.se1p_plan_get_info.restype = i
@@ -251,19 +254,22 @@ def _ptr(t):
 class Plan:
     """An SE1P plan: geometry, tables and device workspace for up to n_max
     particles.  Calls enqueue on the current torch stream of the plan's
-    device unless a stream is given."""
+    device unless a stream is given.  periodic=True plans the triply
+    periodic comparison method (SE3P, se3p_plan_create)."""
 
-    def __init__(self, params: Params, n_max: int, stream=None):
+    def __init__(self, params: Params, n_max: int, stream=None, periodic: bool = False):
         torch = _torch()
         self.params = params
+        self.periodic = bool(periodic)
         self.dtype = torch.float64 if params.precision == FP64 else torch.float32
         self.device = torch.device("cuda", torch.cuda.current_device())
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._stream = s
         h = ctypes.c_void_p()
-        _check(_lib().se1p_plan_create(ctypes.byref(params), int(n_max),
-                                       ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)),
-               "se1p_plan_create")
+        create = _lib().se3p_plan_create if self.periodic else _lib().se1p_plan_create
+        _check(create(ctypes.byref(params), int(n_max), ctypes.c_void_p(s.cuda_stream),
+                      ctypes.byref(h)),
+               "se3p_plan_create" if self.periodic else "se1p_plan_create")
         self._h = h
         info = PlanInfo()
         _check(_lib().se1p_plan_get_info(self._h, ctypes.byref(info)), "se1p_plan_get_info")

@@ -1,0 +1,121 @@
+"""Parity of the triply periodic comparison path (SE3P, se3p_plan_create)
+against the FP64 triply periodic Ewald oracle (oracle.ewald3p), whose pins
+are the published Madelung constants.
+
+Tolerances: rel-RMS 1e-8 in FP64 at parameters whose truncation errors are
+far below it; 1e-5 in FP32; at the paper's own 1e-5 parameters for the
+density-125, xi = 4 systems the error must stay below that tolerance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1611_09538_amd import workloads
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+M_NACL = 1.747564594633182
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _se1p():
+    from paper_1611_09538_amd import se1p
+    return se1p
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _run(x, q, box, xi, M3, P, rc, precision, pad_free=8):
+    se1p = _se1p()
+    dev = _dev()
+    prm = se1p.make_params(box, xi, M3, P, 0, 1.0, rc=rc, pad_free=pad_free,
+                           precision=precision)
+    plan = se1p.Plan(prm, n_max=x.shape[0], periodic=True)
+    dt = plan.dtype
+    phi, E, U = plan.eval(torch.tensor(x, device=dev, dtype=dt),
+                          torch.tensor(q, device=dev, dtype=dt))
+    torch.cuda.synchronize()
+    out = (phi.double().cpu().numpy(), E.double().cpu().numpy(), U.item())
+    plan.close()
+    return out
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_rocksalt_lattice_madelung():
+    _say("SE3P rock-salt lattice, FP64")
+    pts = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], float)
+    x = pts + np.array([0.31, 0.17, 0.43])
+    q = np.array([(-1.0) ** (i + j + k) for i in (0, 1) for j in (0, 1) for k in (0, 1)])
+    phi, E, U = _run(x, q, (2.0, 2.0, 2.0), 3.0, 24, 24, 1.75, _se1p().FP64)
+    _say(f"q phi + M: {np.abs(q * phi + M_NACL).max():.2e}  |E| {np.abs(E).max():.2e}")
+    assert np.abs(q * phi + M_NACL).max() < 1e-9
+    assert np.abs(E).max() < 1e-9
+    assert U == pytest.approx(-4.0 * M_NACL, rel=1e-9)
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-8), ("fp32", 1e-5)])
+def test_random_system_matches_oracle(prec, bar):
+    se1p = _se1p()
+    _say(f"SE3P random neutral system, {prec}")
+    rng = np.random.default_rng(31)
+    box = np.array([1.0, 1.25, 0.75])
+    x = workloads.uniform_positions(rng, 1000, box)
+    q = workloads.neutral_uniform(rng, 1000)
+    if prec == "fp32":
+        x = x.astype(np.float32).astype(np.float64)   # the inputs the GPU sees
+    pr = se1p.FP64 if prec == "fp64" else se1p.FP32
+    P = 24 if prec == "fp64" else 12
+    phi, E, U = _run(x, q, box, 8.0, 24, P, 0.65, pr)
+    po, Eo = oracle.ewald3p_total(x, q, box, 8.0)
+    dphi, dE = _rel(phi, po), _rel(E, Eo)
+    _say(f"rel-rms phi {dphi:.2e}  E {dE:.2e}")
+    assert dphi < bar and dE < bar
+    Uo = 0.5 * float(np.dot(q, po))
+    assert abs(U - Uo) < bar * 0.5 * float(np.abs(q * po).sum())
+
+
+def test_paper_density125_system_at_1e5():
+    # the timing systems of the SE1P / SE3P comparison: uniform density 125,
+    # xi = 4, P = 12, rc = 0.781 (the paper's 1e-5 parameters), scaled to
+    # N = 2000 (L = 2.52, M = 24 keeps h = L / M as at N = 2e4, M = 52)
+    se1p = _se1p()
+    _say("SE3P density-125 system at the 1e-5 parameters, FP64")
+    rng = np.random.default_rng(32)
+    L = 2.52
+    box = np.array([L, L, L])
+    x = workloads.uniform_positions(rng, 2000, box)
+    q = workloads.neutral_uniform(rng, 2000)
+    phi, E, _ = _run(x, q, box, 4.0, 24, 12, 0.781, se1p.FP64)
+    tg = np.arange(0, 2000, 4)
+    po, Eo = oracle.ewald3p_total(x, q, box, 4.0, targets=tg)
+    dphi, dE = _rel(phi[tg], po), _rel(E[tg], Eo)
+    _say(f"rel-rms phi {dphi:.2e}  E {dE:.2e}")
+    assert dphi < 1e-5 and dE < 1e-4
+
+
+def test_stage_calls_rejected_for_periodic_plan():
+    se1p = _se1p()
+    dev = _dev()
+    prm = se1p.make_params((1.0, 1.0, 1.0), 6.0, 16, 8, 0, 1.0, rc=0.5)
+    plan = se1p.Plan(prm, n_max=16, periodic=True)
+    x = torch.rand(16, 3, device=dev, dtype=torch.float64)
+    q = torch.zeros(16, device=dev, dtype=torch.float64)
+    g = torch.zeros(1 << 16, device=dev, dtype=torch.float64)
+    rc = se1p._lib().se1p_spread(plan._h, 16, se1p._ptr(x), se1p._ptr(q), se1p._ptr(g))
+    assert rc == se1p.ERR_UNSUPPORTED
+    plan.close()
+    bad = se1p.make_params((1.03, 1.0, 1.0), 6.0, 16, 8, 0, 1.0, rc=0.5)
+    with pytest.raises(RuntimeError):
+        se1p.Plan(bad, n_max=16, periodic=True)
