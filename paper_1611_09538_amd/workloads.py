@@ -27,6 +27,17 @@ def neutral_uniform(rng, n):
     return q - q.mean()
 
 
+def density125_system(n, seed):
+    """The timing systems of the paper's per-particle timing and SE1P / SE3P
+    comparison examples: n particles uniform in a cube of side
+    L = (n / 125)^(1/3) (number density 125), charges uniform in [-1, 1]
+    shifted to zero sum.  Returns (x, q, box)."""
+    rng = np.random.default_rng(seed)
+    L = (n / 125.0) ** (1.0 / 3.0)
+    box = np.array([L, L, L])
+    return uniform_positions(rng, n, box), neutral_uniform(rng, n), box
+
+
 def uniform_positions(rng, n, box):
     """Positions uniform in [0, L1) x [0, L2) x [0, L3)."""
     box = np.asarray(box, dtype=np.float64)
