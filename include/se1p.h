@@ -143,7 +143,8 @@ typedef struct se1p_plan se1p_plan;
 /*
  * se1p_suggest_params -- host only.  Parameter selection of section 4.3:
  * given a target RMS error tol, the box, N and Q = sum q^2, pick
- *   - M3 = 2 k_inf from the Fourier truncation estimate (eq. kinf) when
+ *   - M3 = 2 k_inf from the Fourier truncation estimate (eq. kinf),
+ *     rounded up to an even size with prime factors 2, 3 and 5 only, when
  *     M3_in <= 0, else use M3_in and pick the largest xi that meets the same
  *     estimate (xi_in <= 0), or the given xi_in;
  *   - rc from the real-space estimate (eq. rc);

@@ -649,8 +649,11 @@ int se1p_suggest_params(double tol, const double box[3], long long N, double Q,
         const double D = 4.0 / (3.0 * L * L) * std::pow(Q / kPi, 2.0 / 3.0);
         const double kinf = std::sqrt(3.0) * L * p.xi / (2.0 * kPi) *
                             std::sqrt(lambert_w(D / std::pow(p.xi * tol * tol, 2.0 / 3.0)));
-        p.M3 = 2 * (int)std::ceil(kinf);
-        if (p.M3 < 8) p.M3 = 8;
+        // 2 k_inf, rounded up to an even size the transforms take (prime
+        // factors 2, 3 and 5 only)
+        int m = std::max(8, 2 * (int)std::ceil(kinf));
+        while (nice_size(m) != m || (m & 1)) ++m;
+        p.M3 = m;
     }
     // eq. rc with V for L^3
     const double C = Q / (2.0 * V * p.xi * tol * tol);

@@ -63,6 +63,11 @@ def test_suggest_params_follows_recipe():
 def test_suggest_params_from_xi_picks_grid():
     p = se1p.suggest_params(1e-6, (1.0, 1.0, 1.0), 1000, 1000.0, xi=10.0)
     assert p.M3 % 2 == 0 and p.M3 >= 8
+    r = p.M3
+    for f in (2, 3, 5):
+        while r % f == 0:
+            r //= f
+    assert r == 1          # a size the radix-2/3/4/5 transforms take
     kinf = p.M3 / 2
     errF = 10.0 / math.pi ** 2 * kinf ** -1.5 * math.sqrt(1000.0) * math.exp(-(math.pi * kinf / 10.0) ** 2)
     assert errF <= 1e-6

@@ -1,0 +1,217 @@
+"""Accuracy suite: the paper's error experiments as GPU checks against the
+FP64 oracle.  Each compares the k-space part (gridding, adaptive transform,
+scaling, gather) with the oracle's k3 != 0 and k3 = 0 sums at the same xi:
+
+  * error vs P against the estimate of eq. approximation_error_oneterm,
+    A exp(-c^2 pi P / 2), c = 0.95, A = sqrt(Q xi L) / L (approximation
+    error figure; every slab upsampled, fine grid);
+  * error vs the number n_l of upsampled slabs (error-vs-P figure for n_l
+    choices);
+  * force error vs the upsampling factor s_l (force example, N = 10, xi = 8);
+  * the finite-size cases: point-wise force error vs distance to the nearest
+    xy edge (case 1) and a +-1 pair with the free charge on the xy diagonal
+    (case 2);
+  * the paper's parameter table for N = 120, L = 10, Q = 1 (each row within
+    3x the error the paper reports for it), and this build's parameter recipe
+    of section 4.3 for the same systems (absolute rms error of the k-space
+    potential within 50x the tolerance: the estimates are not bounds).
+The grid size M = 38 of the force example is replaced by 40 (the transforms
+take radices 2, 3, 4, 5).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1611_09538_amd import workloads
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+C_SHAPE = 0.95
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _se1p():
+    from paper_1611_09538_amd import se1p
+    return se1p
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _kspace_gpu(x, q, box, xi, M3, P, n_l, s_l, pad_free=8):
+    se1p = _se1p()
+    dev = _dev()
+    prm = se1p.make_params(box, xi, M3, P, n_l, s_l, rc=0.0, pad_free=pad_free)
+    plan = se1p.Plan(prm, n_max=x.shape[0])
+    phi, E, _ = plan.eval(torch.tensor(x, device=dev), torch.tensor(q, device=dev),
+                          flags=se1p.KSPACE)
+    torch.cuda.synchronize()
+    out = phi.cpu().numpy(), E.cpu().numpy()
+    plan.close()
+    return out
+
+
+def _kspace_oracle(x, q, box, xi):
+    r = oracle.ewald(x, q, box, xi,
+                     parts=oracle.PARTS_FK | oracle.PARTS_F0 | oracle.PARTS_FIELD)
+    return r["phi_Fk"] + r["phi_F0"], r["E_Fk"] + r["E_F0"]
+
+
+def _rms(a):
+    return float(np.sqrt(np.mean(np.square(a))))
+
+
+def test_error_vs_P_follows_estimate():
+    rng = np.random.default_rng(41)
+    box = np.array([1.0, 1.0, 1.0])
+    x = workloads.uniform_positions(rng, 100, box)
+    q = workloads.neutral_uniform(rng, 100)
+    xi = 15.0
+    Q = float(np.sum(q * q))
+    A = np.sqrt(Q * xi * 1.0) / 1.0
+    po, _ = _kspace_oracle(x, q, box, xi)
+    errs = {}
+    for P in (8, 12, 16, 20, 24):
+        # every slab upsampled (n_l = M3 / 2), s_l = 4: only the Gaussian
+        # truncation and quadrature error of the theorem remains
+        pg, _ = _kspace_gpu(x, q, box, xi, 64, P, 32, 4.0)
+        errs[P] = _rms(pg - po) / A
+        est = np.exp(-C_SHAPE ** 2 * np.pi * P / 2)
+        _say(f"P {P}: scaled rms error {errs[P]:.2e}, estimate {est:.2e}")
+        assert errs[P] < 10 * est + 1e-13
+    assert errs[12] < errs[8] / 20 and errs[20] < errs[16] / 20
+    # single and double precision levels at P = 12 and 24 (section 4.2)
+    assert errs[12] < 1e-6 and errs[24] < 1e-12
+
+
+def test_error_vs_upsampled_slabs():
+    rng = np.random.default_rng(42)
+    box = np.array([1.0, 1.0, 1.0])
+    x = workloads.uniform_positions(rng, 100, box)
+    q = workloads.neutral_uniform(rng, 100)
+    xi = 12.0
+    po, _ = _kspace_oracle(x, q, box, xi)
+    scale = _rms(po)
+    errs = {}
+    for n_l in (0, 2, 4, 32):
+        pg, _ = _kspace_gpu(x, q, box, xi, 64, 24, n_l, 3.0)
+        errs[n_l] = _rms(pg - po) / scale
+        _say(f"n_l {n_l}: rel rms error {errs[n_l]:.2e}")
+    # each pair of upsampled slabs removes orders of magnitude, towards the
+    # floor of upsampling every slab
+    assert errs[2] < errs[0] / 100
+    assert errs[4] < errs[2] / 100
+    assert errs[32] <= errs[4] and errs[4] < 20 * errs[32] and errs[32] < 1e-9
+
+
+def test_force_error_vs_upsampling_factor():
+    rng = np.random.default_rng(43)
+    box = np.array([1.0, 1.0, 1.0])
+    x = workloads.uniform_positions(rng, 10, box)
+    q = workloads.neutral_uniform(rng, 10)
+    xi = 8.0
+    _, Eo = _kspace_oracle(x, q, box, xi)
+    errs = {}
+    for sl in (1.0, 2.0, 3.0, 4.0):
+        _, Eg = _kspace_gpu(x, q, box, xi, 40, 24, 6, sl)
+        errs[sl] = float(np.linalg.norm(Eg - Eo) / np.linalg.norm(Eo))
+        _say(f"s_l {sl}: force rel rms error {errs[sl]:.2e}")
+    assert errs[2.0] < errs[1.0] and errs[4.0] < errs[2.0]
+    assert errs[4.0] < 1e-12           # machine precision with s_l = 4, n_l = 6
+
+
+def test_finite_size_error_vs_edge_distance():
+    rng = np.random.default_rng(44)
+    box = np.array([1.0, 1.0, 1.0])
+    x = workloads.uniform_positions(rng, 500, box)
+    q = workloads.neutral_pm1(rng, 500)
+    xi = 8.0
+    _, Eo = _kspace_oracle(x, q, box, xi)
+    d = np.minimum.reduce([x[:, 0], 1.0 - x[:, 0], x[:, 1], 1.0 - x[:, 1]])
+    for sl in (1.5, 3.0):
+        _, Eg = _kspace_gpu(x, q, box, xi, 32, 28, 4, sl)
+        e = np.sqrt(np.sum((Eg - Eo) ** 2, axis=1)) / 3.0
+        near, far = e[d < 0.05], e[d > 0.25]
+        _say(f"s_l {sl}: point-wise error near edges {near.max():.2e} "
+             f"interior {far.max():.2e} (median {np.median(e):.2e})")
+        _say(f"  medians near {np.median(near):.2e} interior {np.median(far):.2e}")
+        # s_l = 3: no growth towards the free boundaries of the charge box.
+        # s_l = 1.5 is reported only: its upsampled slabs put the periodic
+        # images of the opposite edge within 0.5 L of an edge particle, and
+        # the errors there are several times the interior ones.
+        if sl >= 3.0:
+            assert np.median(near) < 3 * np.median(far) + 1e-14
+            assert near.max() < 3 * far.max() + 1e-14
+
+
+def test_finite_size_pair_on_the_diagonal():
+    box = np.array([1.0, 1.0, 1.0])
+    q = np.array([1.0, -1.0])
+    xi = 8.0
+    errs = []
+    for t in (0.05, 0.2, 0.35, 0.65, 0.8, 0.95):
+        x = np.array([[0.5, 0.5, 0.0], [t, t, 0.1]])
+        _, Eo = _kspace_oracle(x, q, box, xi)
+        _, Eg = _kspace_gpu(x, q, box, xi, 32, 28, 4, 3.0)
+        errs.append(float(np.sqrt(np.sum((Eg[1] - Eo[1]) ** 2)) / 3.0))
+        _say(f"free charge at ({t}, {t}, 0.1): force error {errs[-1]:.2e}")
+    # the error of the free charge stays small wherever it sits on the
+    # diagonal, up to the corners of the charge box
+    assert max(errs) < 1e-9
+
+
+# rows of the paper's parameter table for N = 120, L = 10, Q = 1: xi, tol, M,
+# P, n_l, s_l and the rms error it reports for the k-space potential
+# (M = 52 becomes 54: the transforms take radices 2, 3, 4, 5)
+TABLE = [(1.5, 1e-6, 32, 12, 3, 2.0, 5.4e-7), (3.0, 1e-6, 64, 12, 6, 2.4, 9.4e-7),
+         (1.5, 1e-12, 54, 24, 7, 3.2, 6.7e-13), (3.0, 1e-12, 96, 24, 14, 3.9, 8.3e-13)]
+
+
+def _table_system():
+    rng = np.random.default_rng(45)
+    box = np.array([10.0, 10.0, 10.0])
+    x = workloads.uniform_positions(rng, 120, box)
+    q = workloads.neutral_pm1(rng, 120) / np.sqrt(120.0)    # Q = sum q^2 = 1
+    return x, q, box
+
+
+@pytest.mark.parametrize("xi,tol,M,P,n_l,sl,paper_err", TABLE)
+def test_parameter_table_error_levels(xi, tol, M, P, n_l, sl, paper_err):
+    x, q, box = _table_system()
+    pg, _ = _kspace_gpu(x, q, box, xi, M, P, n_l, sl, pad_free=0)
+    po, _ = _kspace_oracle(x, q, box, xi)
+    err = _rms(pg - po)
+    _say(f"table xi {xi} tol {tol:.0e} M {M} P {P} n_l {n_l} s_l {sl:.2f}: "
+         f"k-space rms error {err:.2e} (paper {paper_err:.1e})")
+    # the paper reports one random system of its own; the rms error of
+    # another draw sits within a small factor of it
+    assert err < 3 * paper_err
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-12])
+@pytest.mark.parametrize("xi", [1.5, 3.0])
+def test_parameter_recipe_kspace_error(tol, xi):
+    se1p = _se1p()
+    x, q, box = _table_system()
+    prm = se1p.suggest_params(tol, box, 120, Q=1.0, xi=xi)
+    pg, _ = _kspace_gpu(x, q, box, xi, prm.M3, prm.P, prm.n_l, prm.s_l,
+                        pad_free=prm.pad_free)
+    po, _ = _kspace_oracle(x, q, box, xi)
+    # the estimates behind the recipe (eqs. kinf and approximation_error_
+    # oneterm) are estimates of the absolute rms error, not bounds.  Inverted
+    # exactly they give grids and supports below the paper's own table (M 54
+    # and P 10 where it takes 64 and 12 for xi = 3 at 1e-6; its rows are
+    # checked above) and errors of 3 to 40 times tol; inverted at tol / 10
+    # they reproduce the table's M and P within one size.
+    err = _rms(pg - po)
+    _say(f"recipe tol {tol:.0e}, xi {xi}: M3 {prm.M3} P {prm.P} n_l {prm.n_l} "
+         f"s_l {prm.s_l:.2f}: k-space rms error {err:.2e}")
+    assert err < 50 * tol
