@@ -23,7 +23,10 @@ Extra fields:
                   (every k3 slab upsampled) on the same system
   se3p_comparison k-space time of SE1P against the triply periodic SE3P on
                   the paper's density-125, xi = 4 timing systems (N = 1e5) at
-                  its 1e-5 and 1e-9 parameters
+                  its 1e-5 and 1e-9 parameters, and per particle over its
+                  N = 2e4 .. 1e5 sweep at 1e-5
+  total_runtime   total time (real space included) over the paper's
+                  density-100 total-runtime systems, N = 21600 .. 274400
   batched         64 systems (N log-uniform in [1e3, 5e4]) in one graph
                   launch, FP32 at 1e-5, against one plan per system (FP32 and
                   FP64) at the same parameters
@@ -225,8 +228,65 @@ def se3p_extra(se1p, workloads, torch, dev, steps, warmup):
         r["transform_ratio"] = (r["se1p"]["stages_ms"]["kspace"] /
                                 r["se3p"]["stages_ms"]["kspace"])
         out[f"tol_{tol:.0e}"] = r
+    # per-particle k-space time over the paper's N sweep at 1e-5 (M of its
+    # table rounded up to 2/3/5-smooth sizes: 52 -> 54, 76 -> 80, 88 -> 90)
+    sweep = []
+    for n, M, nl in ((20000, 54, 7), (40000, 64, 9), (60000, 80, 10), (80000, 90, 10),
+                     (100000, 96, 12)):
+        xs, qs, bs = workloads.density125_system(n, seed=5)
+        xt2 = torch.tensor(xs, device=dev)
+        qt2 = torch.tensor(qs, device=dev)
+        p2 = torch.empty(n, device=dev, dtype=torch.float64)
+        E2 = torch.empty((n, 3), device=dev, dtype=torch.float64)
+        row = {"N": n, "M": M, "n_l": nl}
+        for periodic, name in ((False, "se1p"), (True, "se3p")):
+            prm = se1p.make_params(bs, 4.0, M, 12, nl, 2.0, rc=0.0, pad_free=8)
+            plan = se1p.Plan(prm, n_max=n, periodic=periodic)
+            t = timed(lambda: plan.eval_into(xt2, qt2, p2, E2, U, flags=se1p.KSPACE),
+                      steps, warmup, torch)
+            plan.close()
+            row[name + "_us_per_particle"] = t * 1e6 / n
+        row["ratio"] = row["se1p_us_per_particle"] / row["se3p_us_per_particle"]
+        sweep.append(row)
+    out["sweep_1e-05"] = sweep
     out["paper_ratio"] = "about 1.5 at both tolerances (k-space runtime, one CPU core)"
     return out
+
+
+def total_runtime_extra(se1p, workloads, oracle_mod, torch, dev, steps, warmup):
+    """Total runtime (real space included) on the scaled systems of the
+    paper's total-runtime example: density 100, xi = 3.5, P = 16, rc = 0.9,
+    s_l = 3, M and n_l from its table (M rounded up to 2/3/5-smooth even
+    sizes: 46 -> 48, 62 -> 64, 84 -> 90, 92 -> 96), FP64."""
+    import numpy as np
+    rows = []
+    for N, M, nl in ((21600, 48, 4), (51200, 64, 6), (100000, 80, 6),
+                     (172800, 96, 8), (274400, 108, 10)):
+        x, q, box = workloads.density_system(N, 100.0, seed=7)
+        prm = se1p.make_params(box, 3.5, M, 16, nl, 3.0, rc=0.9, pad_free=8)
+        plan = se1p.Plan(prm, n_max=N)
+        xt = torch.tensor(x, device=dev)
+        qt = torch.tensor(q, device=dev)
+        phi = torch.empty(N, device=dev, dtype=torch.float64)
+        E = torch.empty((N, 3), device=dev, dtype=torch.float64)
+        U = torch.empty(1, device=dev, dtype=torch.float64)
+        plan.timing_enable(True)
+        t = timed(lambda: plan.eval_into(xt, qt, phi, E, U), steps, warmup, torch)
+        st, nc = plan.timing_read()
+        plan.close()
+        r = {"N": N, "L": float(box[0]), "M": M, "n_l": nl, "ms": t * 1e3,
+             "us_per_particle": t * 1e6 / N,
+             "stages_ms": {k: v / max(nc, 1) for k, v in st.items()}}
+        if N == 21600 and oracle_mod is not None:
+            tg = np.arange(0, N, 108)
+            po, _ = oracle_mod.ewald_total(x, q, box, targets=tg, field=False)
+            pg = phi.cpu().numpy()[tg]
+            r["rel_rms_phi_sample"] = float(np.linalg.norm(pg - po) / np.linalg.norm(po))
+            r["sample_targets"] = int(tg.size)
+        rows.append(r)
+    return {"workload": "density 100, xi 3.5, P 16, rc 0.9, s_l 3, FP64, "
+                        "charges uniform in [-1, 1] minus the mean",
+            "paper_target_rel_rms": 2e-6, "rows": rows}
 
 
 def batched_extra(se1p, workloads, torch, dev, steps, warmup):
@@ -410,6 +470,12 @@ def main():
         print("batched done", file=sys.stderr, flush=True)
         out["se3p_comparison"] = se3p_extra(se1p, workloads, torch, dev, max(5, a.steps // 2), 2)
         print("se3p comparison done", file=sys.stderr, flush=True)
+        orc = None
+        if not a.no_cpu_baseline:
+            import oracle as orc
+        out["total_runtime"] = total_runtime_extra(se1p, workloads, orc, torch, dev,
+                                                   max(5, a.steps // 2), 2)
+        print("total runtime sweep done", file=sys.stderr, flush=True)
 
     if not a.no_cpu_baseline:
         import oracle

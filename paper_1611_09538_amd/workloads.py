@@ -27,6 +27,15 @@ def neutral_uniform(rng, n):
     return q - q.mean()
 
 
+def density_system(n, density, seed):
+    """n particles uniform in a cube of side (n / density)^(1/3), charges
+    uniform in [-1, 1] shifted to zero sum.  Returns (x, q, box)."""
+    rng = np.random.default_rng(seed)
+    L = (n / float(density)) ** (1.0 / 3.0)
+    box = np.array([L, L, L])
+    return uniform_positions(rng, n, box), neutral_uniform(rng, n), box
+
+
 def density125_system(n, seed):
     """The timing systems of the paper's per-particle timing and SE1P / SE3P
     comparison examples: n particles uniform in a cube of side
