@@ -232,6 +232,15 @@ __device__ __forceinline__ void block_coords(int b, const BinGeo& bg, int& bz,
     bx = (bz & 1) ? bg.nbx - 1 - bxs : bxs;
 }
 
+// XCD-aware work order.  The dispatcher deals workgroups round-robin to the
+// 8 XCDs, each with its own L2; this bijection of [0, n) gives XCD r the
+// contiguous range of the logical order, so work units that are neighbours
+// in that order (and re-read the same data) share one L2.
+__device__ __forceinline__ unsigned xcd_order(unsigned L, unsigned n) {
+    const unsigned C = (n + 7) / 8, d = 8 * C - n, r = L % 8, k = L / 8;
+    return r * C - (r > 8 - d ? r - (8 - d) : 0) + k;
+}
+
 // Lex and block cell keys of one particle.
 template <typename T>
 __device__ __forceinline__ void cell_keys(const T* __restrict__ xin, long long i,
@@ -509,8 +518,14 @@ __global__ __launch_bounds__(64 * spread_waves(P)) void spread_kernel(
     const T* __restrict__ wyq, const int* __restrict__ pcy,
     const int* __restrict__ cstart, T* __restrict__ Hpart,
     long long pstride, Geo g, int CZ, int KP) {
+    // (z chunk, y tile, x tile) in XCD order: the tiles that re-read a
+    // particle's weights share one L2
+    const unsigned ntile = gridDim.x * gridDim.y * gridDim.z;
+    const unsigned lg = xcd_order(
+        blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), ntile);
     spread_body<T, P>(wz, wxp, wyq, pcy, cstart, Hpart, pstride, g, CZ, KP,
-                      blockIdx.x, blockIdx.y, blockIdx.z);
+                      (int)(lg % gridDim.x), (int)((lg / gridDim.x) % gridDim.y),
+                      (int)(lg / (gridDim.x * gridDim.y)));
 }
 
 template <typename T>
@@ -976,8 +991,10 @@ __global__ __launch_bounds__(64) void gather_kernel(
     const int* __restrict__ pcz, const int* __restrict__ perm,
     const int* __restrict__ cstart, Geo g, BinGeo bg, int CH, T scale,
     T* __restrict__ phi_out, T* __restrict__ E_out) {
+    // blocks in XCD order: neighbouring columns, whose footprints overlap,
+    // stage their planes through one L2
     gather_body<T, P>(Ht, ptx, pty, ptz, pcx, pcy, pcz, perm, cstart, g, bg, CH,
-                      scale, phi_out, E_out, blockIdx.x);
+                      scale, phi_out, E_out, (int)xcd_order(blockIdx.x, gridDim.x));
 }
 
 // ------------------------------------------------------------------------
