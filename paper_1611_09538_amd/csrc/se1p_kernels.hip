@@ -1140,9 +1140,12 @@ __device__ __forceinline__ void realspace_body(
                 const int j = kq + 4 * i;
                 const T dx = xt - cx_[j], dy = yt - cy_[j], dz = zt - cz_[j];
                 const T r2 = dx * dx + dy * dy + dz * dz;
-                const bool in = act && (j < n) && (r2 <= rc2) && (r2 > (T)0);
+                // bitwise, not short-circuit: straight-line compares instead
+                // of a branch per candidate (all j < 64 are in the LDS batch)
+                const bool in = (j < n) & (r2 <= rc2) & (r2 > (T)0);
                 mask |= (unsigned int)in << i;
             }
+            if (!act) mask = 0u;
             // pass 2: every lane works through its own in-range candidates
             while (__any(mask != 0u)) {
                 if (mask != 0u) {
