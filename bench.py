@@ -25,6 +25,8 @@ Extra fields:
                   the paper's density-125, xi = 4 timing systems (N = 1e5) at
                   its 1e-5 and 1e-9 parameters, and per particle over its
                   N = 2e4 .. 1e5 sweep at 1e-5
+  ik_field        the field by ik-differentiation (SE1P_FIELD_IK) on the
+                  headline system: time and accuracy on the oracle sample
   total_runtime   total time (real space included) over the paper's
                   density-100 total-runtime systems, N = 21600 .. 274400
   batched         64 systems (N log-uniform in [1e3, 5e4]) in one graph
@@ -501,6 +503,25 @@ def main():
             "phi": float(np.linalg.norm(pg[tg] - phi_ref) / np.linalg.norm(phi_ref)),
             "E": float(np.linalg.norm(Eg[tg] - E_ref) / np.linalg.norm(E_ref)),
             "targets": nt}
+
+    if not a.no_extras and prec == se1p.FP64:
+        # the field by ik-differentiation (three more inverse transforms and
+        # potential-only gathers) against the analytic gradient of the gather
+        Eik = torch.empty_like(E)
+        plan.timing_enable(True)
+        t_ik = timed(lambda: plan.eval_into(xt, qt, phi, Eik, U, flags=se1p.ALL | se1p.FIELD_IK),
+                     max(5, a.steps // 2), 2, torch)
+        st_ik, nc_ik = plan.timing_read()
+        plan.timing_enable(False)
+        st_ik = {k: v / max(nc_ik, 1) for k, v in st_ik.items()}
+        ik = {"ms_per_step": t_ik * 1e3, "analytic_ms_per_step": ms_step,
+              "kspace_ms": st_ik["kspace"], "gather_ms": st_ik["gather"],
+              "analytic_kspace_ms": st_ms["kspace"], "analytic_gather_ms": st_ms["gather"]}
+        if not a.no_cpu_baseline:
+            Ek = Eik.cpu().numpy()
+            ik["rel_rms_E_sample"] = float(np.linalg.norm(Ek[tg] - E_ref) / np.linalg.norm(E_ref))
+        out["ik_field"] = ik
+        print("ik field done", file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

@@ -76,6 +76,12 @@ extern "C" {
                                   vector (used for adjoint products); the
                                   result is the discrete operator applied to
                                   q, not a physical Ewald sum */
+#define SE1P_FIELD_IK    128u  /* E^F by ik-differentiation, the route of
+                                  eq. force_fourier the paper sets aside for
+                                  the analytic gradient (eq. force_se1p):
+                                  -i k times the scaled spectrum, three more
+                                  inverse transforms and potential-only
+                                  gathers; SE1P plans only */
 
 /*
  * Method parameters (Algorithm 1 input, section 4.3 recipe).
@@ -210,7 +216,8 @@ int se1p_set_stream(se1p_plan* plan, void* stream);
  *   energy     device, one double out: U = 1/2 sum q phi over the requested
  *              components, or NULL.
  *   flags      SE1P_KSPACE | SE1P_REAL | SE1P_SELF, optionally with
- *              SE1P_CHECK_INPUT and SE1P_NO_NEUTRAL.
+ *              SE1P_CHECK_INPUT, SE1P_NO_NEUTRAL and SE1P_FIELD_IK
+ *              (SE1P_ERR_UNSUPPORTED on an SE3P plan).
  * Components left out contribute zero.  Without SE1P_CHECK_INPUT,
  * out-of-box x/y are clamped to the box edge cells (memory-safe, result
  * unspecified).

@@ -428,6 +428,10 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     }
     add(&pl.G, (size_t)pl.slab_elems * cs);
     add(&pl.Ht, (size_t)(pl.pstride + 64) * pl.es);   // rows are read in halves
+    if (!pl.periodic3) {
+        add(&pl.Gk, 3 * (size_t)pl.slab_elems * cs);
+        add(&pl.Htk, 3 * (size_t)(pl.pstride + 64) * pl.es);
+    }
     add(&pl.S0, (size_t)pl.n0[0] * pl.n0[1] * pl.es);
     add(&pl.tw, (size_t)pl.tw_elems * cs);
     add((void**)&pl.d_slabs, pl.slabs.size() * sizeof(SlabDesc));
@@ -524,14 +528,33 @@ int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
             if ((rc = run_kspace<T>(pl, (const T*)pl.Hper, 1, (T)1, (T)1, (T*)pl.Htp))) return rc;
             if ((rc = launch_unfold<T>((const T*)pl.Htp, pl.g, pl.gf, (T*)pl.Ht, pl.stream)))
                 return rc;
+        } else if (flags & SE1P_FIELD_IK) {
+            if ((rc = launch_kspace_ik<T>((const T*)pl.Hpart, pl.KP, pl.pstride, pl.g,
+                                          pl.nslab, pl.d_slabs, pl.slabs.data(), pl.dz,
+                                          (const cplx<T>*)pl.tw, (const T*)pl.S0,
+                                          (cplx<T>*)pl.Fz, (cplx<T>*)pl.G,
+                                          (cplx<T>*)pl.Gk, pl.slab_elems, (T*)pl.Ht,
+                                          (T*)pl.Htk, pl.pstride + 64, pl.stream)))
+                return rc;
         } else {
             if ((rc = run_kspace<T>(pl, (const T*)pl.Hpart, pl.KP, (T)1, (T)1, (T*)pl.Ht))) return rc;
         }
         tmark(pl, 3);
         DevParticles<T> blk = particles<T>(pl, false);
-        if ((rc = launch_gather<T>((const T*)pl.Ht, blk, N, pl.g, pl.bg, (T)1,
-                                   (T*)pl.phiF, (T*)pl.EF, pl.stream)))
+        if (flags & SE1P_FIELD_IK) {
+            // the potential and each field component from its own grid
+            if ((rc = launch_gather_phi<T>((const T*)pl.Ht, blk, pl.g, pl.bg, (T)1,
+                                           (T*)pl.phiF, 1, pl.stream)))
+                return rc;
+            for (int d = 0; d < 3; ++d)
+                if ((rc = launch_gather_phi<T>((const T*)pl.Htk + d * (pl.pstride + 64), blk,
+                                               pl.g, pl.bg, (T)1, (T*)pl.EF + d, 3,
+                                               pl.stream)))
+                    return rc;
+        } else if ((rc = launch_gather<T>((const T*)pl.Ht, blk, N, pl.g, pl.bg, (T)1,
+                                          (T*)pl.phiF, (T*)pl.EF, pl.stream))) {
             return rc;
+        }
         mask |= 2 | 4 | 8;
     } else {
         tmark(pl, 2);
@@ -814,7 +837,9 @@ int se1p_set_stream(se1p_plan* plan, void* stream) {
 int se1p_eval(se1p_plan* pl, long long N, const void* x, const void* q,
               void* phi, void* efield, double* energy, unsigned flags) {
     if (!pl || !x || !q) return SE1P_ERR_ARG;
-    if (flags & ~(SE1P_ALL | SE1P_CHECK_INPUT | SE1P_NO_NEUTRAL)) return SE1P_ERR_ARG;
+    if (flags & ~(SE1P_ALL | SE1P_CHECK_INPUT | SE1P_NO_NEUTRAL | SE1P_FIELD_IK))
+        return SE1P_ERR_ARG;
+    if ((flags & SE1P_FIELD_IK) && pl->periodic3) return SE1P_ERR_UNSUPPORTED;
     if ((flags & SE1P_ALL) == 0) return SE1P_ERR_ARG;
     if (N < 1) return SE1P_ERR_ARG;
     if (N > pl->n_max) return SE1P_ERR_TOO_MANY;

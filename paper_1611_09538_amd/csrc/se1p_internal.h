@@ -117,6 +117,21 @@ int launch_realspace(const DevParticles<T>& lex, const DevParticles<T>& blk,
                      double rc, int nparts, bool periodic3, T* phi_out, T* E_out,
                      hipStream_t s);
 
+// The k-space solve with the field by ik-differentiation: potential grid Ht
+// and the three field-component grids Htk + d gstride (d = 0, 1, 2); Gk is
+// workspace for three copies of the slab data (slab_elems each).
+template <typename T>
+int launch_kspace_ik(const T* Hin, int KP, long long pstride, const Geo& g,
+                     int nslab, const SlabDesc* d_slabs, const SlabDesc* h_slabs,
+                     const FftDesc& dz, const cplx<T>* tw, const T* S0,
+                     cplx<T>* Fz, cplx<T>* G, cplx<T>* Gk, long long slab_elems,
+                     T* Ht, T* Htk, long long gstride, hipStream_t s);
+
+// Potential-only gather of one grid into out[perm * ostride].
+template <typename T>
+int launch_gather_phi(const T* Ht, const DevParticles<T>& blk, const Geo& g,
+                      const BinGeo& bg, T scale, T* out, int ostride, hipStream_t s);
+
 // SE3P: sum the KP partial extended grids (geometry g) onto the periodic
 // grid (geometry gf, Mt = M), and copy the periodic grid back out over the
 // extended grid for the gather.

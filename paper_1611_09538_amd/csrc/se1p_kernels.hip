@@ -714,13 +714,35 @@ __device__ __forceinline__ T slab_scale(const SlabDesc& sd, int kx, int ky,
 
 constexpr int kColsPerBlock = 4;
 
+// Wavenumber component d (0: x, 1: y, 2: z) of the mode (kx, ky, n3) of a
+// slab, for ik-differentiation; zero at an even length's Nyquist index,
+// whose sine mode the grid cannot carry.
+__device__ __forceinline__ double slab_k(const SlabDesc& sd, int kx, int ky,
+                                         const Geo& g, int d) {
+    const double twopi = 6.283185307179586476925286766559;
+    if (d == 0) {
+        if (2 * kx == sd.n1) return 0.0;
+        const int f = (kx <= sd.n1 / 2) ? kx : kx - sd.n1;
+        return twopi * f / (sd.n1 * g.h);
+    }
+    if (d == 1) {
+        if (2 * ky == sd.n2) return 0.0;
+        const int f = (ky <= sd.n2 / 2) ? ky : ky - sd.n2;
+        return twopi * f / (sd.n2 * g.h);
+    }
+    if (2 * sd.n3 == g.M3) return 0.0;
+    return twopi * sd.n3 / g.L3;
+}
+
 // Fused column pass: zero-padded FFT along x, scaling, inverse FFT along x,
-// restriction to the first Mt1 rows, for ncb columns ky.
+// restriction to the first Mt1 rows, for ncb columns ky.  dir >= 0 also
+// multiplies the scaled spectrum by -i k_dir (the field component dir of
+// the potential, E = -grad phi, by ik-differentiation).
 template <typename T>
 __device__ __forceinline__ void cols_body(
     cplx<T>* __restrict__ G, const SlabDesc* __restrict__ slabs, const Geo& g,
     const cplx<T>* __restrict__ tw, const T* __restrict__ S0, int cb,
-    int slab, int ncb) {
+    int slab, int ncb, int dir = -1) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SlabDesc& sd = slabs[slab];   // by reference: no private copy
     const int n1 = sd.n1, n2 = sd.n2;
@@ -745,7 +767,15 @@ __device__ __forceinline__ void cols_body(
     for (int idx = threadIdx.x; idx < n1 * ncb; idx += blockDim.x) {
         const int c = idx / n1, kx = idx - c * n1;
         const T s = (c < nc) ? slab_scale<T>(sd, kx, k0 + c, g, S0) : (T)0;
-        X[c * stride + kx] = cscale<T>(X[c * stride + kx], s);
+        cplx<T> v = cscale<T>(X[c * stride + kx], s);
+        if (dir >= 0) {
+            // (-i k)(a + i b) = k b - i k a
+            const T k = (T)slab_k(sd, kx, k0 + c, g, dir);
+            const T a = v.x;
+            v.x = k * v.y;
+            v.y = -k * a;
+        }
+        X[c * stride + kx] = v;
     }
     __syncthreads();
     cplx<T>* Z = fft_lds<T>(X, Y, ncb, stride, sd.d1,
@@ -759,8 +789,8 @@ __device__ __forceinline__ void cols_body(
 template <typename T>
 __global__ __launch_bounds__(256) void cols_kernel(
     cplx<T>* __restrict__ G, const SlabDesc* __restrict__ slabs, Geo g,
-    const cplx<T>* __restrict__ tw, const T* __restrict__ S0) {
-    cols_body<T>(G, slabs, g, tw, S0, blockIdx.x, blockIdx.y, kColsPerBlock);
+    const cplx<T>* __restrict__ tw, const T* __restrict__ S0, int dir) {
+    cols_body<T>(G, slabs, g, tw, S0, blockIdx.x, blockIdx.y, kColsPerBlock, dir);
 }
 
 // Inverse FFT along y, restriction to the first Mt2 columns.
@@ -814,14 +844,15 @@ __global__ __launch_bounds__(256) void rowinv_kernel(
 // (FP32 evaluates exp directly), z weights are one exp per plane.
 constexpr int kGatherStage = 12; // staged plane values per lane in flight
 
-template <typename T, int P>
+template <typename T, int P, bool FIELD = true>
 __device__ __forceinline__ void gather_body(
     const T* __restrict__ Ht, const T* __restrict__ ptx,
     const T* __restrict__ pty, const T* __restrict__ ptz,
     const int* __restrict__ pcx, const int* __restrict__ pcy,
     const int* __restrict__ pcz, const int* __restrict__ perm,
     const int* __restrict__ cstart, const Geo& g, const BinGeo& bg, int CH,
-    T scale, T* __restrict__ phi_out, T* __restrict__ E_out, int bid) {
+    T scale, T* __restrict__ phi_out, T* __restrict__ E_out, int bid,
+    int phi_stride = 1) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     constexpr int HP = P / 2;         // the y window is swept in two halves
@@ -956,13 +987,15 @@ __device__ __forceinline__ void gather_body(
 #pragma unroll
                         for (int u = 0; u < HP; ++u) {
                             sy = fma(wy[u], hv[u], sy);
-                            sty = fma(ty[u], hv[u], sty);
+                            if constexpr (FIELD) sty = fma(ty[u], hv[u], sty);
                         }
                         const T wxz = wx * wzv;
                         phi = fma(wxz, sy, phi);
-                        ey = fma(wxz, sty, ey);
-                        ex = fma(ddx * wxz, sy, ex);
-                        ez = fma(wx * tzw, sy, ez);
+                        if constexpr (FIELD) {
+                            ey = fma(wxz, sty, ey);
+                            ex = fma(ddx * wxz, sy, ex);
+                            ez = fma(wx * tzw, sy, ez);
+                        }
                     }
                 }
             }
@@ -971,8 +1004,8 @@ __device__ __forceinline__ void gather_body(
         }
         if (act) {
             const long long o = perm[p];
-            if (phi_out) phi_out[o] = scale * phi;
-            if (E_out) {
+            if (phi_out) phi_out[o * phi_stride] = scale * phi;
+            if (FIELD && E_out) {
                 const T f = scale * (T)2 * a;
                 E_out[3 * o] = f * ex;
                 E_out[3 * o + 1] = f * ey;
@@ -1327,6 +1360,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void re
     const int chunk = blockIdx.x / nparts, part = blockIdx.x - chunk * nparts;
     realspace_body<T, PXY>(blk, lx, g, xi, rc, R, phi_out + (long long)part * N,
                            E_out + 3LL * part * N, 0, N, chunk, part, nparts);
+}
+
+// ------------------------------------------------------------------------
+// potential-only gather (ik-differentiation gathers each field component
+// from its own grid with the potential's weights)
+// ------------------------------------------------------------------------
+template <typename T, int P>
+__global__ __launch_bounds__(64) void gather_phi_kernel(
+    const T* __restrict__ Ht, const T* __restrict__ ptx,
+    const T* __restrict__ pty, const T* __restrict__ ptz,
+    const int* __restrict__ pcx, const int* __restrict__ pcy,
+    const int* __restrict__ pcz, const int* __restrict__ perm,
+    const int* __restrict__ cstart, Geo g, BinGeo bg, int CH, T scale,
+    T* __restrict__ out, int ostride) {
+    gather_body<T, P, false>(Ht, ptx, pty, ptz, pcx, pcy, pcz, perm, cstart, g, bg, CH,
+                             scale, out, nullptr, (int)xcd_order(blockIdx.x, gridDim.x),
+                             ostride);
 }
 
 // ------------------------------------------------------------------------
@@ -1785,7 +1835,7 @@ int launch_kspace(const T* Hin, int KP, long long pstride, T in_scale,
     const size_t csm = 2 * (size_t)kColsPerBlock * (n1max + 1) * cs;
     dim3 cgrid((n2max + kColsPerBlock - 1) / kColsPerBlock, nslab);
     hipLaunchKernelGGL(cols_kernel<T>, cgrid, dim3(256), csm, s, G, d_slabs, g,
-                       tw, S0);
+                       tw, S0, -1);
     SE1P_CHECK_LAUNCH();
     hipLaunchKernelGGL(rowinv_kernel<T>, rgrid, dim3(256), rsm, s, G, Fz,
                        d_slabs, g, tw);
@@ -1794,6 +1844,79 @@ int launch_kspace(const T* Hin, int KP, long long pstride, T in_scale,
                        out_scale, Ht, g, dz, tw);
     SE1P_CHECK_LAUNCH();
     return 0;
+}
+
+// The k-space solve with the field by ik-differentiation: the forward
+// transforms once, then per output (the potential and the three field
+// components) the column pass with its multiplier on a copy of the
+// row-transformed slabs, the inverse row and z transforms.  Gk holds three
+// copies of G (slab_elems each); Htk three output grids of gstride values.
+template <typename T>
+int launch_kspace_ik(const T* Hin, int KP, long long pstride, const Geo& g,
+                     int nslab, const SlabDesc* d_slabs, const SlabDesc* h_slabs,
+                     const FftDesc& dz, const cplx<T>* tw, const T* S0,
+                     cplx<T>* Fz, cplx<T>* G, cplx<T>* Gk, long long slab_elems,
+                     T* Ht, T* Htk, long long gstride, hipStream_t s) {
+    const size_t cs = sizeof(cplx<T>);
+    const unsigned ncb = (unsigned)((g.ncol + kZfftCols - 1) / kZfftCols);
+    const size_t zsm = 2 * (kZfftCols / 2) * (size_t)(g.M3 + 1) * cs;
+    hipLaunchKernelGGL(zfft_kernel<T>, dim3(ncb), dim3(256), zsm, s, Hin, KP,
+                       pstride, (T)1, Fz, g, dz, tw);
+    SE1P_CHECK_LAUNCH();
+    int n1max = 0, n2max = 0;
+    for (int i = 0; i < nslab; ++i) {
+        n1max = n1max > h_slabs[i].n1 ? n1max : h_slabs[i].n1;
+        n2max = n2max > h_slabs[i].n2 ? n2max : h_slabs[i].n2;
+    }
+    const size_t rsm = 2 * (size_t)kRowsPerBlock * n2max * cs;
+    dim3 rgrid((g.Mt1 + kRowsPerBlock - 1) / kRowsPerBlock, nslab);
+    hipLaunchKernelGGL(rowfwd_kernel<T>, rgrid, dim3(256), rsm, s, Fz, G,
+                       d_slabs, g, tw);
+    SE1P_CHECK_LAUNCH();
+    for (int d = 0; d < 3; ++d)
+        if (hipMemcpyAsync(Gk + d * slab_elems, G, (size_t)slab_elems * cs,
+                           hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return -5;
+    const size_t csm = 2 * (size_t)kColsPerBlock * (n1max + 1) * cs;
+    dim3 cgrid((n2max + kColsPerBlock - 1) / kColsPerBlock, nslab);
+    for (int d = -1; d < 3; ++d) {
+        cplx<T>* Gd = d < 0 ? G : Gk + d * slab_elems;
+        T* Hd = d < 0 ? Ht : Htk + d * gstride;
+        hipLaunchKernelGGL(cols_kernel<T>, cgrid, dim3(256), csm, s, Gd, d_slabs, g,
+                           tw, S0, d);
+        SE1P_CHECK_LAUNCH();
+        hipLaunchKernelGGL(rowinv_kernel<T>, rgrid, dim3(256), rsm, s, Gd, Fz,
+                           d_slabs, g, tw);
+        SE1P_CHECK_LAUNCH();
+        hipLaunchKernelGGL(zifft_kernel<T>, dim3(ncb), dim3(256), zsm, s, Fz,
+                           (T)1, Hd, g, dz, tw);
+        SE1P_CHECK_LAUNCH();
+    }
+    return 0;
+}
+
+template <typename T, int P>
+static int gather_phi_p(const T* Ht, const DevParticles<T>& blk, const Geo& g,
+                        const BinGeo& bg, T scale, T* out, int ostride, hipStream_t s) {
+    const unsigned nb = (unsigned)(bg.nbx * bg.nby * bg.nbz) * bg.CH;
+    const size_t lds = 2 * (size_t)(bg.BX + P - 1) * bg.ldy * sizeof(T);
+    hipLaunchKernelGGL((gather_phi_kernel<T, P>), dim3(nb), dim3(64), lds, s, Ht,
+                       blk.tx, blk.ty, blk.tz, blk.cx, blk.cy, blk.cz, blk.perm,
+                       blk.start, g, bg, bg.CH, scale, out, ostride);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+template <typename T>
+int launch_gather_phi(const T* Ht, const DevParticles<T>& blk, const Geo& g,
+                      const BinGeo& bg, T scale, T* out, int ostride, hipStream_t s) {
+    switch (g.P) {
+#define SE1P_GPHI_CASE(PP) \
+    case PP: return gather_phi_p<T, PP>(Ht, blk, g, bg, scale, out, ostride, s);
+        SE1P_P_CASES(SE1P_GPHI_CASE)
+#undef SE1P_GPHI_CASE
+        default: return -8;
+    }
 }
 
 template <typename T, int P>
@@ -2080,6 +2203,14 @@ int batch_occupancy(int queue, int P, size_t lds, int* blocks_per_cu) {
                                      const DevParticles<T>&, long long,         \
                                      const Geo&, const BinGeo&, double, double, \
                                      int, bool, T*, T*, hipStream_t);           \
+    template int launch_kspace_ik<T>(const T*, int, long long, const Geo&, int, \
+                                     const SlabDesc*, const SlabDesc*,          \
+                                     const FftDesc&, const cplx<T>*, const T*,  \
+                                     cplx<T>*, cplx<T>*, cplx<T>*, long long,   \
+                                     T*, T*, long long, hipStream_t);           \
+    template int launch_gather_phi<T>(const T*, const DevParticles<T>&,         \
+                                      const Geo&, const BinGeo&, T, T*, int,    \
+                                      hipStream_t);                             \
     template int launch_fold<T>(const T*, int, long long, const Geo&,          \
                                 const Geo&, T*, hipStream_t);                   \
     template int launch_unfold<T>(const T*, const Geo&, const Geo&, T*,        \

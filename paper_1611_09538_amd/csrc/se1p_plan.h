@@ -57,6 +57,7 @@ struct se1p_plan {
     void* Hpart = nullptr;
     long long pstride = 0;
     void *Hper = nullptr, *Htp = nullptr;   // SE3P: folded grid, transform output
+    void *Gk = nullptr, *Htk = nullptr;     // ik-differentiation: slab copies, field grids
     void* Fz = nullptr;
     void* G = nullptr;
     void* Ht = nullptr;

@@ -36,6 +36,7 @@ SELF = 4
 ALL = 7
 CHECK_INPUT = 16
 NO_NEUTRAL = 32
+FIELD_IK = 128
 BATCH_EAGER = 64
 
 

@@ -1,0 +1,105 @@
+"""The k-space field by ik-differentiation (SE1P_FIELD_IK) against the
+analytic gradient of the gather (eq. force_se1p) and the FP64 oracle.
+
+ik-differentiation multiplies the scaled spectrum by -i k (eq. force_fourier
+route) and gathers each field component with the potential's weights; the
+potential itself takes the same grid and weights as the default path.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1611_09538_amd import workloads
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _se1p():
+    from paper_1611_09538_amd import se1p
+    return se1p
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _eval(plan, x, q, flags):
+    dev = _dev()
+    phi, E, U = plan.eval(torch.tensor(x, device=dev, dtype=plan.dtype),
+                          torch.tensor(q, device=dev, dtype=plan.dtype), flags=flags)
+    torch.cuda.synchronize()
+    return phi.double().cpu().numpy(), E.double().cpu().numpy(), U.item()
+
+
+@pytest.mark.parametrize("n", [500, 3000])
+def test_ik_field_matches_analytic_and_oracle(n):
+    se1p = _se1p()
+    _say(f"ik-differentiation, FP64, N {n}")
+    c = workloads.CASES["small"]
+    rng = np.random.default_rng(51)
+    box = np.asarray(c["box"], dtype=np.float64)
+    x = workloads.uniform_positions(rng, n, box)
+    q = workloads.neutral_uniform(rng, n)
+    prm = se1p.make_params(box, c["xi"], c["M3"], c["P"], c["nl"], c["sl"],
+                           rc=c["rc"], pad_free=c.get("pad_free", 0))
+    plan = se1p.Plan(prm, n_max=n)
+    pa, Ea, Ua = _eval(plan, x, q, se1p.ALL)
+    pk, Ek, Uk = _eval(plan, x, q, se1p.ALL | se1p.FIELD_IK)
+    plan.close()
+    tg = np.arange(0, n, max(1, n // 300))
+    po, Eo = oracle.ewald_total(x, q, box, targets=tg)
+    d_phi = _rel(pk, pa)
+    e_an, e_ik = _rel(Ea[tg], Eo), _rel(Ek[tg], Eo)
+    _say(f"phi ik vs analytic {d_phi:.1e}; field vs oracle: analytic {e_an:.2e}, "
+         f"ik {e_ik:.2e}; ik vs analytic {_rel(Ek, Ea):.2e}")
+    # same grid, same weights: the potential does not change
+    assert d_phi < 1e-14 and abs(Uk - Ua) < 1e-14 * abs(Ua)
+    # both fields meet the FP64 path's target against the oracle
+    assert e_an < 1e-8 and e_ik < 1e-8
+
+
+def test_ik_field_fp32():
+    se1p = _se1p()
+    _say("ik-differentiation, FP32 vs FP64 analytic")
+    c = workloads.CASES["small"]
+    rng = np.random.default_rng(52)
+    box = np.asarray(c["box"], dtype=np.float64)
+    x = workloads.uniform_positions(rng, 2000, box).astype(np.float32).astype(np.float64)
+    q = workloads.neutral_uniform(rng, 2000)
+    p64 = se1p.make_params(box, c["xi"], c["M3"], c["P"], c["nl"], c["sl"], rc=c["rc"])
+    p32 = se1p.make_params(box, c["xi"], c["M3"], 12, c["nl"], c["sl"], rc=c["rc"],
+                           precision=se1p.FP32)
+    a = se1p.Plan(p64, n_max=2000)
+    _, Ea, _ = _eval(a, x, q, se1p.ALL)
+    a.close()
+    b = se1p.Plan(p32, n_max=2000)
+    _, Ek, _ = _eval(b, x, q, se1p.ALL | se1p.FIELD_IK)
+    b.close()
+    err = _rel(Ek, Ea)
+    _say(f"FP32 ik field vs FP64 analytic: {err:.2e}")
+    assert err < 1e-5
+
+
+def test_ik_rejected_for_periodic_plan():
+    se1p = _se1p()
+    dev = _dev()
+    prm = se1p.make_params((1.0, 1.0, 1.0), 6.0, 16, 8, 0, 1.0, rc=0.5)
+    plan = se1p.Plan(prm, n_max=16, periodic=True)
+    x = torch.rand(16, 3, device=dev, dtype=torch.float64)
+    q = torch.zeros(16, device=dev, dtype=torch.float64)
+    with pytest.raises(se1p.SE1PError) as e:
+        plan.eval(x, q, flags=se1p.ALL | se1p.FIELD_IK)
+    assert e.value.code == se1p.ERR_UNSUPPORTED
+    plan.close()
