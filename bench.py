@@ -508,11 +508,12 @@ def main():
         # the field by ik-differentiation (three more inverse transforms and
         # potential-only gathers) against the analytic gradient of the gather
         Eik = torch.empty_like(E)
-        plan.timing_enable(True)
-        t_ik = timed(lambda: plan.eval_into(xt, qt, phi, Eik, U, flags=se1p.ALL | se1p.FIELD_IK),
+        pik = plan_for(se1p, c, box, N, prec)
+        pik.timing_enable(True)
+        t_ik = timed(lambda: pik.eval_into(xt, qt, phi, Eik, U, flags=se1p.ALL | se1p.FIELD_IK),
                      max(5, a.steps // 2), 2, torch)
-        st_ik, nc_ik = plan.timing_read()
-        plan.timing_enable(False)
+        st_ik, nc_ik = pik.timing_read()
+        pik.close()
         st_ik = {k: v / max(nc_ik, 1) for k, v in st_ik.items()}
         ik = {"ms_per_step": t_ik * 1e3, "analytic_ms_per_step": ms_step,
               "kspace_ms": st_ik["kspace"], "gather_ms": st_ik["gather"],
