@@ -168,7 +168,7 @@ void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
         const int BZ = bzs[iz];
         for (int iy = 0; iy < 4; ++iy) {
             const int BY = bys[iy];
-            // planes are staged in 16-byte chunks: with ldy == BY (mod 32)
+            // planes are staged in 16-byte chunks: with ldy == BY (mod nb)
             // the pitch holds whole chunks only if BY does
             if ((BY * (int)pl.es) % 16) continue;
             for (int BX = 1; BX * BY <= nbank; ++BX) {

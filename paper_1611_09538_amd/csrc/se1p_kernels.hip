@@ -832,17 +832,16 @@ __global__ __launch_bounds__(256) void rowinv_kernel(
 // ------------------------------------------------------------------------
 // gather (step 6) and its gradient
 // ------------------------------------------------------------------------
-// Lanes are particles: one wave takes a chunk of up to 64 particles of one
-// block of BX x BY x BZ cells (block blockIdx.x / CH, chunk slot
-// blockIdx.x % CH; further chunks of a block are strided by CH).  The grid
-// planes the chunk's supports touch are staged one at a time in LDS
-// (coalesced loads of the block's (BX + P - 1) x (BY + P - 1) footprint,
-// the next plane prefetched into registers while the current one is used);
-// each lane then reads its own P x P window of the plane from LDS.  y
-// weights live in registers, x weights follow the Gaussian-gridding
-// recurrence w(u+1) = w(u) r(u), r(u+1) = r(u) exp(-2 alpha h^2) in FP64
-// (FP32 evaluates exp directly), z weights are one exp per plane.
-constexpr int kGatherStage = 12; // staged plane values per lane in flight
+// Lanes are particles: work unit bid takes chunks of 64 consecutive
+// particles of one block of BX x BY x BZ cells (block bid / CH, chunk slot
+// bid % CH; further chunks of a block are strided by CH).  The grid planes
+// the chunk's supports touch are staged one at a time in LDS (global_load_lds
+// of the block's (BX + P - 1) x (BY + P - 1) footprint, the next plane in
+// flight while the current one is read); each lane then reads its own P x P
+// window of the plane from LDS.  y weights live in registers, x weights
+// follow the Gaussian-gridding recurrence w(u+1) = w(u) r(u),
+// r(u+1) = r(u) exp(-2 alpha h^2) in FP64 (FP32 evaluates exp directly),
+// z weights are one exp per plane.
 
 template <typename T, int P, bool FIELD = true>
 __device__ __forceinline__ void gather_body(
