@@ -7,7 +7,10 @@ term, FP64 energy) of the N = 1e5 FP64 system in a unit box periodic in z
 memory.  Prints one JSON line.
 
 Extra fields:
-  stages_ms       per-stage times from HIP events on the plan's stream
+  stages_ms       per-stage times from HIP events on the plan's stream, from
+                  a run of their own after the timed region (the timed region
+                  records events only around the real-space sum: every event
+                  between two kernels costs time of its own)
   roofline        the dominant kernel (the real-space sum): algorithmic flops
                   (exact in-range pair count x flops per pair) over its
                   event-timed duration, against the MI355X vector peak;
@@ -142,6 +145,19 @@ def timed(fn, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps
 
 
+def timed_and_staged(plan, fn, steps, warmup, torch):
+    """Seconds per call with no events recorded, then the per-stage times in
+    ms from a second run with events around every stage (each event between
+    two kernels costs time of its own, so the two are not taken together)."""
+    t = timed(fn, steps, warmup, torch)
+    plan.timing_select(None)
+    plan.timing_enable(True)
+    timed(fn, steps, 0, torch)
+    st, nc = plan.timing_read()
+    plan.timing_enable(False)
+    return t, {k: v / max(nc, 1) for k, v in st.items()}
+
+
 def plan_for(se1p, c, box, n, precision):
     prm = se1p.make_params(box, c["xi"], c["M3"], c["P"], c["nl"], c["sl"],
                            rc=c["rc"], pad_free=c["pad_free"], precision=precision)
@@ -162,12 +178,9 @@ def fp32_extra(se1p, workloads, torch, dev, steps, warmup):
         phi = torch.empty(N, device=dev, dtype=dt)
         E = torch.empty((N, 3), device=dev, dtype=dt)
         U = torch.empty(1, device=dev, dtype=torch.float64)
-        plan.timing_enable(True)
-        s = timed(lambda: plan.eval_into(xt, qt, phi, E, U), steps, warmup, torch)
-        st, nc = plan.timing_read()
-        plan.timing_enable(False)
-        out[name] = {"ms_per_step": s * 1e3, "particles_per_s": N / s,
-                     "stages_ms": {k: v / max(nc, 1) for k, v in st.items()}}
+        s, st = timed_and_staged(plan, lambda: plan.eval_into(xt, qt, phi, E, U),
+                                 steps, warmup, torch)
+        out[name] = {"ms_per_step": s * 1e3, "particles_per_s": N / s, "stages_ms": st}
         plan.close()
         del xt, qt, phi, E, U
     out["speedup_fp32_over_fp64"] = out["f64"]["ms_per_step"] / out["f32"]["ms_per_step"]
@@ -272,13 +285,11 @@ def total_runtime_extra(se1p, workloads, oracle_mod, torch, dev, steps, warmup):
         phi = torch.empty(N, device=dev, dtype=torch.float64)
         E = torch.empty((N, 3), device=dev, dtype=torch.float64)
         U = torch.empty(1, device=dev, dtype=torch.float64)
-        plan.timing_enable(True)
-        t = timed(lambda: plan.eval_into(xt, qt, phi, E, U), steps, warmup, torch)
-        st, nc = plan.timing_read()
+        t, st = timed_and_staged(plan, lambda: plan.eval_into(xt, qt, phi, E, U),
+                                 steps, warmup, torch)
         plan.close()
         r = {"N": N, "L": float(box[0]), "M": M, "n_l": nl, "ms": t * 1e3,
-             "us_per_particle": t * 1e6 / N,
-             "stages_ms": {k: v / max(nc, 1) for k, v in st.items()}}
+             "us_per_particle": t * 1e6 / N, "stages_ms": st}
         if N == 21600 and oracle_mod is not None:
             tg = np.arange(0, N, 108)
             po, _ = oracle_mod.ewald_total(x, q, box, targets=tg, field=False)
@@ -372,6 +383,9 @@ def main():
         plan.eval_into(xt, qt, phi, E, U)
     torch.cuda.synchronize()
 
+    # the timed region records two events per step, around the real-space
+    # sum (the kernel the roofline prices), on the plan's stream
+    plan.timing_select(["realspace"])
     plan.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -381,10 +395,17 @@ def main():
     t1 = time.perf_counter()
     stages, ncalls = plan.timing_read()
     plan.timing_enable(False)
+    rs_ms = stages["realspace"] / max(ncalls, 1)
     print(f"timed {a.steps} steps", file=sys.stderr, flush=True)
 
     ms_step = (t1 - t0) * 1e3 / a.steps
     value = N / (ms_step * 1e-3)
+    # per-stage times from a run of their own with events around every stage
+    plan.timing_select(None)
+    plan.timing_enable(True)
+    timed(lambda: plan.eval_into(xt, qt, phi, E, U), max(5, a.steps // 2), 0, torch)
+    stages, ncalls = plan.timing_read()
+    plan.timing_enable(False)
     st_ms = {k: v / max(ncalls, 1) for k, v in stages.items()}
     kspace_ms = st_ms["bin"] + st_ms["spread"] + st_ms["kspace"] + st_ms["gather"]
 
@@ -392,12 +413,12 @@ def main():
     peak = PEAK_TFLOPS[dname]
     npairs = pair_count(x, box, c["rc"])
     rs_flops = PAIR_FLOPS[dname] * npairs
-    rs_ach = rs_flops / (st_ms["realspace"] * 1e-3) / 1e12
+    rs_ach = rs_flops / (rs_ms * 1e-3) / 1e12
     roof = {"kernel": "realspace_kernel", "bound": "alu", "achieved": rs_ach,
             "peak": peak, "unit": "TFLOP/s", "frac": rs_ach / peak,
             "traffic": traffic_for("realspace_kernel", a.case),
             "pairs_per_launch": npairs, "flops_per_pair": PAIR_FLOPS[dname],
-            "algorithmic_flops_per_launch": rs_flops, "avg_ms": st_ms["realspace"]}
+            "algorithmic_flops_per_launch": rs_flops, "avg_ms": rs_ms}
     g_fl = gather_flops(N, P)
     g_ach = g_fl / (st_ms["gather"] * 1e-3) / 1e12
     w = 8 if dname == "f64" else 4
@@ -509,12 +530,10 @@ def main():
         # potential-only gathers) against the analytic gradient of the gather
         Eik = torch.empty_like(E)
         pik = plan_for(se1p, c, box, N, prec)
-        pik.timing_enable(True)
-        t_ik = timed(lambda: pik.eval_into(xt, qt, phi, Eik, U, flags=se1p.ALL | se1p.FIELD_IK),
-                     max(5, a.steps // 2), 2, torch)
-        st_ik, nc_ik = pik.timing_read()
+        t_ik, st_ik = timed_and_staged(
+            pik, lambda: pik.eval_into(xt, qt, phi, Eik, U, flags=se1p.ALL | se1p.FIELD_IK),
+            max(5, a.steps // 2), 2, torch)
         pik.close()
-        st_ik = {k: v / max(nc_ik, 1) for k, v in st_ik.items()}
         ik = {"ms_per_step": t_ik * 1e3, "analytic_ms_per_step": ms_step,
               "kspace_ms": st_ik["kspace"], "gather_ms": st_ik["gather"],
               "analytic_kspace_ms": st_ms["kspace"], "analytic_gather_ms": st_ms["gather"]}

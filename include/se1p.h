@@ -265,9 +265,17 @@ int se1p_gather(se1p_plan* plan, long long N, const void* x,
  * writes the summed milliseconds of each stage over the recorded calls
  * (ms_sum has SE1P_NSTAGE entries) and the number of calls; stages a call
  * skipped contribute zero.  Up to 4096 calls are kept.
+ *
+ * Each recorded event sits between two kernels of the stream and costs time
+ * of its own.  se1p_timing_select(plan, stages) limits the recording to the
+ * stages whose bits are set in `stages` (bit s for stage s; the default is
+ * every stage), so that a timed run can price one stage with two events per
+ * call; unselected stages read zero.  It clears earlier records and returns
+ * SE1P_ERR_ARG for 0 or bits at or above SE1P_NSTAGE.
  */
 #define SE1P_NSTAGE 6
 int se1p_timing_enable(se1p_plan* plan, int enable);
+int se1p_timing_select(se1p_plan* plan, unsigned stages);
 int se1p_timing_read(se1p_plan* plan, double* ms_sum, int* ncalls);
 
 /* ---- batches: many independent systems in one set of launches ----------

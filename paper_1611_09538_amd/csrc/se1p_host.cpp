@@ -88,8 +88,12 @@ struct Buf {
 namespace {
 constexpr int kTimingMaxCalls = 4096;
 
+// boundary b opens stage b and closes stage b - 1: its event is recorded
+// only when one of the two is selected
 void tmark(se1p_plan& pl, int boundary) {
     if (!pl.timing || pl.tcalls >= kTimingMaxCalls) return;
+    const unsigned near = (pl.tstages << 1 | pl.tstages) >> boundary;
+    if (!(near & 1u)) return;
     const size_t k = (size_t)pl.tcalls * (SE1P_NSTAGE + 1) + boundary;
     if (k < pl.tev.size()) (void)hipEventRecord(pl.tev[k], pl.stream);
 }
@@ -766,6 +770,14 @@ int se1p_timing_enable(se1p_plan* pl, int enable) {
     return SE1P_OK;
 }
 
+int se1p_timing_select(se1p_plan* pl, unsigned stages) {
+    if (!pl) return SE1P_ERR_ARG;
+    if (stages == 0u || (stages >> SE1P_NSTAGE) != 0u) return SE1P_ERR_ARG;
+    pl->tstages = stages;
+    pl->tcalls = 0;
+    return SE1P_OK;
+}
+
 int se1p_timing_read(se1p_plan* pl, double* ms_sum, int* ncalls) {
     if (!pl || !ms_sum) return SE1P_ERR_ARG;
     for (int s = 0; s < SE1P_NSTAGE; ++s) ms_sum[s] = 0.0;
@@ -778,6 +790,7 @@ int se1p_timing_read(se1p_plan* pl, double* ms_sum, int* ncalls) {
     for (int c = 0; c < pl->tcalls; ++c) {
         const hipEvent_t* e = &pl->tev[(size_t)c * (SE1P_NSTAGE + 1)];
         for (int s = 0; s < SE1P_NSTAGE; ++s) {
+            if (!((pl->tstages >> s) & 1u)) continue;
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, e[s], e[s + 1]) != hipSuccess) return SE1P_ERR_HIP;
             ms_sum[s] += ms;

@@ -72,6 +72,7 @@ struct se1p_plan {
 
     // stage timing: events[call][boundary], boundaries 0..SE1P_NSTAGE
     int timing = 0;
+    unsigned tstages = (1u << SE1P_NSTAGE) - 1u;   // stages whose events are recorded
     int tcalls = 0;
     std::vector<hipEvent_t> tev;
     std::vector<unsigned char> tmask;   // stages run per call

@@ -134,7 +134,7 @@ EXPORTS = [
     "se1p_suggest_params", "se1p_plan_create", "se1p_plan_destroy",
     "se1p_plan_get_info", "se1p_set_stream", "se1p_eval", "se1p_spread",
     "se1p_kspace_solve", "se1p_gather", "se1p_error_string", "se1p_version",
-    "se1p_timing_enable", "se1p_timing_read", "se1p_calibrate",
+    "se1p_timing_enable", "se1p_timing_select", "se1p_timing_read", "se1p_calibrate",
     "se1p_autotune", "se1p_batch_create", "se1p_batch_destroy",
     "se1p_batch_eval", "se1p_batch_get_info", "se1p_batch_system_info",
     "se3p_plan_create",
@@ -183,6 +183,8 @@ def _lib():
     lib.se1p_gather.argtypes = [vp, ll, vp, vp, vp, vp]
     lib.se1p_timing_enable.restype = i
     lib.se1p_timing_enable.argtypes = [vp, i]
+    lib.se1p_timing_select.restype = i
+    lib.se1p_timing_select.argtypes = [vp, ctypes.c_uint]
     lib.se1p_timing_read.restype = i
     lib.se1p_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i)]
     lib.se1p_calibrate.restype = i
@@ -330,6 +332,11 @@ class Plan:
 
     def timing_enable(self, on=True):
         _check(_lib().se1p_timing_enable(self._h, 1 if on else 0), "se1p_timing_enable")
+
+    def timing_select(self, stages=None):
+        """Record events only around the named stages (None: every stage)."""
+        bits = (1 << NSTAGE) - 1 if stages is None else sum(1 << STAGES.index(s) for s in stages)
+        _check(_lib().se1p_timing_select(self._h, bits), "se1p_timing_select")
 
     def timing_read(self):
         """(dict stage -> summed ms, number of calls); synchronises."""

@@ -231,6 +231,37 @@ def test_deterministic_bitwise():
         assert torch.equal(u, v)
 
 
+def test_stage_timing_selection():
+    # events around the selected stages only; the others read zero, and the
+    # outputs do not depend on what is recorded
+    dev = _dev()
+    se1p = _se1p()
+    _say("stage timing selection")
+    x, q, box, _ = workloads.make_case("small")
+    plan, c = _plan("small", x.shape[0])
+    xt, qt = torch.tensor(x, device=dev), torch.tensor(q, device=dev)
+    ref = plan.eval(xt, qt)
+    plan.timing_select(["realspace", "bin"])
+    plan.timing_enable(True)
+    out = [plan.eval(xt, qt) for _ in range(3)]
+    st, nc = plan.timing_read()
+    assert nc == 3
+    assert st["realspace"] > 0 and st["bin"] > 0
+    assert all(st[k] == 0 for k in ("spread", "kspace", "gather", "combine"))
+    plan.timing_select(None)
+    plan.timing_enable(True)
+    plan.eval(xt, qt)
+    st, nc = plan.timing_read()
+    assert nc == 1 and all(v > 0 for v in st.values())
+    plan.timing_enable(False)
+    for o in out:
+        for u, v in zip(o, ref):
+            assert torch.equal(u, v)
+    for bad in (0, 1 << se1p.NSTAGE):
+        assert se1p._lib().se1p_timing_select(plan._h, bad) == se1p.ERR_ARG
+    plan.close()
+
+
 def test_input_errors():
     dev = _dev()
     se1p = _se1p()
