@@ -419,7 +419,7 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     pl.scan_bytes = std::max(scan_temp_bytes(pl.bg.ncell_lex + 1),
                              scan_temp_bytes(pl.bg.ncell_blk + 1)) + 256;
     add(&pl.scan_tmp, pl.scan_bytes);
-    const int PW = p.P + 2 * kPad;
+    const int PW = p.P + 2 * weight_pad((int)pl.es);
     add(&pl.wz, (size_t)N * p.P * pl.es);
     add(&pl.wxp, (size_t)N * PW * pl.es);
     add(&pl.wyq, (size_t)N * PW * pl.es);

@@ -340,12 +340,13 @@ __global__ void bin_gather_kernel(const T* __restrict__ xin,
 // spreading (step 2)
 // ------------------------------------------------------------------------
 // Per particle (lex order): z weights wz[P] (wave-uniform in the spread
-// kernel) and zero-padded x weights wxp[P + 2 kPad], q * y weights wyq.
-// One weight per thread, so that the stores are coalesced: elements
-// [0, N PW) are wxp, [N PW, 2 N PW) wyq and [2 N PW, 2 N PW + N P) wz.
+// kernel) and x weights wxp[PW], q * y weights wyq[PW], PW = P + 2 pad with
+// pad = weight_pad(sizeof(T)) zeros on each side.  One weight per thread, so
+// that the stores are coalesced: elements [0, N PW) are wxp, [N PW, 2 N PW)
+// wyq and [2 N PW, 2 N PW + N P) wz.
 template <typename T, int P>
 constexpr long long spread_weight_count(long long N) {
-    return N * (2 * (P + 2 * kPad) + P);
+    return N * (2 * (P + 2 * weight_pad((int)sizeof(T))) + P);
 }
 
 template <typename T, int P>
@@ -355,7 +356,8 @@ __device__ __forceinline__ void spread_weight_elem(const DevParticles<T>& lx,
                                                    T* __restrict__ wz,
                                                    T* __restrict__ wxp,
                                                    T* __restrict__ wyq) {
-    constexpr int PW = P + 2 * kPad;
+    constexpr int pad = weight_pad((int)sizeof(T));
+    constexpr int PW = P + 2 * pad;
     const T h = (T)g.h, a = (T)g.alpha;
     const long long nxy = N * PW;
     if (i < 2 * nxy) {
@@ -363,7 +365,7 @@ __device__ __forceinline__ void spread_weight_elem(const DevParticles<T>& lx,
         const long long j = isy ? i - nxy : i;
         const long long p = j / PW;
         // distance to grid point cx + 1 + u - P/2 (array index) in units of h
-        const int u = (int)(j - p * PW) - kPad;
+        const int u = (int)(j - p * PW) - pad;
         T w = 0;
         if (u >= 0 && u < P) {
             const T t = isy ? lx.ty[p] : lx.tx[p];
@@ -407,7 +409,8 @@ __device__ __forceinline__ void spread_body(
     const int* __restrict__ cstart, T* __restrict__ Hpart,
     long long pstride, const Geo& g, int CZ, int KP, int tbx, int tby,
     int jc) {
-    constexpr int PW = P + 2 * kPad;
+    constexpr int pad = weight_pad((int)sizeof(T));
+    constexpr int PW = P + 2 * pad;
     constexpr int W = spread_waves(P);
     __shared__ T red[W > 1 ? W : 1][64];
     const int lane = threadIdx.x & 63;
@@ -468,14 +471,29 @@ __device__ __forceinline__ void spread_body(
                 const int cx = cxlo + k;
                 const int s = __builtin_amdgcn_readlane(rsA, k);
                 const int e = __builtin_amdgcn_readlane(reA, k);
-                const int offx = lx - (cx + 1) + kPad;
+                // support index of this lane's column for the row, and of
+                // its y point for each particle: the weight is zero outside
+                // [0, P).  Padded rows are read as they are; unpadded ones
+                // with the index clamped into the particle's row.
+                const int ux = lx - (cx + 1);
+                const bool vx = (unsigned)ux < (unsigned)P;
+                const int offx = pad > 0 ? ux + pad : min(max(ux, 0), P - 1);
+                auto coef = [&](int pp, int cyp) -> T {
+                    const int uy = ly - (cyp + 1);
+                    if constexpr (pad > 0) {
+                        return wxp[(long long)pp * PW + offx] *
+                               wyq[(long long)pp * PW + uy + pad];
+                    } else {
+                        const T wy = wyq[(long long)pp * PW + min(max(uy, 0), P - 1)];
+                        const T wx = wxp[(long long)pp * PW + offx];
+                        return (vx && (unsigned)uy < (unsigned)P) ? wx * wy : (T)0;
+                    }
+                };
                 int p = s + wv;
                 for (; p + W < e; p += 2 * W) {
                     const int cyA = pcy[p], cyB = pcy[p + W];
-                    const T cA = wxp[(long long)p * PW + offx] *
-                                 wyq[(long long)p * PW + ly - (cyA + 1) + kPad];
-                    const T cB = wxp[(long long)(p + W) * PW + offx] *
-                                 wyq[(long long)(p + W) * PW + ly - (cyB + 1) + kPad];
+                    const T cA = coef(p, cyA);
+                    const T cB = coef(p + W, cyB);
                     const T* __restrict__ zA = wz + (long long)p * P;
                     const T* __restrict__ zB = wz + (long long)(p + W) * P;
 #pragma unroll
@@ -485,8 +503,7 @@ __device__ __forceinline__ void spread_body(
                 }
                 if (p < e) {
                     const int cyA = pcy[p];
-                    const T cA = wxp[(long long)p * PW + offx] *
-                                 wyq[(long long)p * PW + ly - (cyA + 1) + kPad];
+                    const T cA = coef(p, cyA);
                     const T* __restrict__ zA = wz + (long long)p * P;
 #pragma unroll
                     for (int d = 0; d < P; ++d) acc[d] = fma(cA, zA[d], acc[d]);
@@ -1573,7 +1590,7 @@ __global__ void bspread_weights_kernel(DevParticles<T> lx, long long N,
                                        T* __restrict__ wyq) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= spread_weight_count<T, P>(N)) return;
-    constexpr int PW = P + 2 * kPad;
+    constexpr int PW = P + 2 * weight_pad((int)sizeof(T));
     const long long nxy = N * PW;
     const long long p = i < 2 * nxy ? (i % nxy) / PW : (i - 2 * nxy) / P;
     spread_weight_elem<T, P>(lx, N, i, sys[sys_of[p]].g, wz, wxp, wyq);
