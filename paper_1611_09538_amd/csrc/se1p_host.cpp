@@ -407,9 +407,7 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     std::vector<std::pair<void**, size_t>> req;
     auto add = [&](void** ptr, size_t bytes) { req.push_back({ptr, (bytes + 255) & ~size_t(255)}); };
     add((void**)&pl.key_lex, N * 4);
-    add((void**)&pl.key_blk, N * 4);
     add((void**)&pl.slot_lex, N * 4);
-    add((void**)&pl.slot_blk, N * 4);
     add((void**)&pl.cnt_lex, (pl.bg.ncell_lex + 1) * 4);
     add((void**)&pl.cnt_blk, (pl.bg.ncell_blk + 1) * 4);
     for (int k = 0; k < 4; ++k) { add((void**)&pl.lex_i[k], N * 4); add((void**)&pl.blk_i[k], N * 4); }
@@ -488,8 +486,8 @@ template <typename T>
 int run_bin(se1p_plan& pl, long long N, const void* x, const void* q) {
     DevParticles<T> lex = particles<T>(pl, true), blk = particles<T>(pl, false);
     return launch_bin<T>((const T*)x, (const T*)q, N, pl.g, pl.bg, pl.key_lex,
-                         pl.key_blk, pl.slot_lex, pl.slot_blk, pl.cnt_lex,
-                         pl.cnt_blk, lex, blk, pl.scan_tmp, pl.scan_bytes,
+                         pl.slot_lex, pl.cnt_lex, pl.cnt_blk, lex, blk,
+                         pl.scan_tmp, pl.scan_bytes,
                          pl.stream);
 }
 

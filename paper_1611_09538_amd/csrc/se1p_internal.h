@@ -86,10 +86,9 @@ struct DevParticles {        // sorted copies of the particles in one order
 
 template <typename T>
 int launch_bin(const T* x_in, const T* q_in, long long N, const Geo& g,
-               const BinGeo& bg, int* key_lex, int* key_blk, int* slot_lex,
-               int* slot_blk, int* cnt_lex, int* cnt_blk,
-               DevParticles<T>& lex, DevParticles<T>& blk, void* scan_tmp,
-               size_t scan_tmp_bytes, hipStream_t s);
+               const BinGeo& bg, int* key_lex, int* slot_lex, int* cnt_lex,
+               int* cnt_blk, DevParticles<T>& lex, DevParticles<T>& blk,
+               void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s);
 
 template <typename T>
 int launch_spread(const DevParticles<T>& lex, long long N, const Geo& g,

@@ -258,22 +258,68 @@ __device__ __forceinline__ void cell_keys(const T* __restrict__ xin, long long i
     kb = b * bg.cpb + (izs * bg.BX + ix) * bg.BY + iy;
 }
 
+// Lex cell key of each particle and its slot in the cell (counting sort).
 template <typename T>
 __global__ void bin_keys_kernel(const T* __restrict__ xin, long long N, Geo g,
-                                BinGeo bg, int* __restrict__ key_lex,
-                                int* __restrict__ key_blk,
+                                int* __restrict__ key_lex,
                                 int* __restrict__ slot_lex,
-                                int* __restrict__ slot_blk,
-                                int* __restrict__ cnt_lex,
-                                int* __restrict__ cnt_blk) {
+                                int* __restrict__ cnt_lex) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    int kl, kb;
-    cell_keys<T>(xin, i, g, bg, kl, kb);
+    T zw;
+    int cx, cy, cz;
+    cell_of<T>(xin[3 * i], xin[3 * i + 1], xin[3 * i + 2], g, zw, cx, cy, cz);
+    const int kl = (cz * g.M1 + cx) * g.M2 + cy;
     key_lex[i] = kl;
-    key_blk[i] = kb;
     slot_lex[i] = atomicAdd(&cnt_lex[kl], 1);
-    slot_blk[i] = atomicAdd(&cnt_blk[kb], 1);
+}
+
+// The block order numbers the same cells as the lex order: lex cell of the
+// block-order cell kb (the inverse of the block key of cell_keys), or -1
+// for the cells of partial blocks beyond the grid.
+__device__ __forceinline__ long long lex_of_blk(long long kb, const Geo& g,
+                                                const BinGeo& bg) {
+    const int b = (int)(kb / bg.cpb);
+    const int r = (int)(kb - (long long)b * bg.cpb);
+    const int izs = r / (bg.BX * bg.BY);
+    const int ix = (r / bg.BY) % bg.BX;
+    const int iy = r % bg.BY;
+    const int iz = (b & 1) ? bg.BZ - 1 - izs : izs;
+    int bz, bx, by;
+    block_coords(b, bg, bz, bx, by);
+    const int cz = bz * bg.BZ + iz, cx = bx * bg.BX + ix, cy = by * bg.BY + iy;
+    if (cz >= g.M3 || cx >= g.M1 || cy >= g.M2) return -1;
+    return ((long long)cz * g.M1 + cx) * g.M2 + cy;
+}
+
+// Counts of the block-order cells from the lex cell starts (entry
+// ncell_blk, the scan's total, is zero).
+__global__ void bin_blk_counts_kernel(long long ncell_blk, Geo g, BinGeo bg,
+                                      const int* __restrict__ lex_start,
+                                      int* __restrict__ cnt_blk) {
+    const long long kb = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (kb > ncell_blk) return;
+    int n = 0;
+    if (kb < ncell_blk) {
+        const long long c = lex_of_blk(kb, g, bg);
+        if (c >= 0) n = lex_start[c + 1] - lex_start[c];
+    }
+    cnt_blk[kb] = n;
+}
+
+// Each block-order cell takes the entries of its lex cell in the same
+// order (input index order, after bin_sort_cells_kernel).
+__global__ void bin_blk_perm_kernel(long long ncell_blk, Geo g, BinGeo bg,
+                                    const int* __restrict__ lex_start,
+                                    const int* __restrict__ lex_perm,
+                                    const int* __restrict__ blk_start,
+                                    int* __restrict__ blk_perm) {
+    const long long kb = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (kb >= ncell_blk) return;
+    const int o = blk_start[kb], n = blk_start[kb + 1] - o;
+    if (n == 0) return;
+    const int s = lex_start[lex_of_blk(kb, g, bg)];
+    for (int k = 0; k < n; ++k) blk_perm[o + k] = lex_perm[s + k];
 }
 
 __global__ void bin_scatter_kernel(long long N, const int* __restrict__ key,
@@ -1771,33 +1817,34 @@ int launch_fill_int(int* p, long long n, int v, hipStream_t s) {
 
 template <typename T>
 int launch_bin(const T* x_in, const T* q_in, long long N, const Geo& g,
-               const BinGeo& bg, int* key_lex, int* key_blk, int* slot_lex,
-               int* slot_blk, int* cnt_lex, int* cnt_blk,
-               DevParticles<T>& lex, DevParticles<T>& blk, void* scan_tmp,
-               size_t scan_tmp_bytes, hipStream_t s) {
+               const BinGeo& bg, int* key_lex, int* slot_lex, int* cnt_lex,
+               int* cnt_blk, DevParticles<T>& lex, DevParticles<T>& blk,
+               void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s) {
+    // counting sort into the lex order; the block order is then a
+    // permutation of whole lex cells
     int rc;
     if ((rc = launch_fill_int(cnt_lex, bg.ncell_lex + 1, 0, s))) return rc;
-    if ((rc = launch_fill_int(cnt_blk, bg.ncell_blk + 1, 0, s))) return rc;
     hipLaunchKernelGGL(bin_keys_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0, s,
-                       x_in, N, g, bg, key_lex, key_blk, slot_lex, slot_blk,
-                       cnt_lex, cnt_blk);
+                       x_in, N, g, key_lex, slot_lex, cnt_lex);
     SE1P_CHECK_LAUNCH();
     size_t tb = scan_tmp_bytes;
     if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb, cnt_lex, lex.start,
                                          (int)(bg.ncell_lex + 1), s) != hipSuccess)
         return -5;
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(N, 256)), dim3(256), 0, s,
+                       N, key_lex, slot_lex, lex.start, lex.perm);
+    hipLaunchKernelGGL(bin_sort_cells_kernel, dim3(nblk(bg.ncell_lex, 256)),
+                       dim3(256), 0, s, bg.ncell_lex, lex.start, lex.perm);
+    hipLaunchKernelGGL(bin_blk_counts_kernel, dim3(nblk(bg.ncell_blk + 1, 256)),
+                       dim3(256), 0, s, bg.ncell_blk, g, bg, lex.start, cnt_blk);
+    SE1P_CHECK_LAUNCH();
     tb = scan_tmp_bytes;
     if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb, cnt_blk, blk.start,
                                          (int)(bg.ncell_blk + 1), s) != hipSuccess)
         return -5;
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(N, 256)), dim3(256), 0, s,
-                       N, key_lex, slot_lex, lex.start, lex.perm);
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(N, 256)), dim3(256), 0, s,
-                       N, key_blk, slot_blk, blk.start, blk.perm);
-    hipLaunchKernelGGL(bin_sort_cells_kernel, dim3(nblk(bg.ncell_lex, 256)),
-                       dim3(256), 0, s, bg.ncell_lex, lex.start, lex.perm);
-    hipLaunchKernelGGL(bin_sort_cells_kernel, dim3(nblk(bg.ncell_blk, 256)),
-                       dim3(256), 0, s, bg.ncell_blk, blk.start, blk.perm);
+    hipLaunchKernelGGL(bin_blk_perm_kernel, dim3(nblk(bg.ncell_blk, 256)), dim3(256),
+                       0, s, bg.ncell_blk, g, bg, lex.start, lex.perm, blk.start,
+                       blk.perm);
     hipLaunchKernelGGL(bin_gather_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0,
                        s, x_in, q_in, N, g, lex);
     hipLaunchKernelGGL(bin_gather_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0,
@@ -2221,8 +2268,8 @@ int batch_occupancy(int queue, int P, size_t lds, int* blocks_per_cu) {
 // explicit instantiations
 #define SE1P_INST(T)                                                           \
     template int launch_bin<T>(const T*, const T*, long long, const Geo&,       \
-                               const BinGeo&, int*, int*, int*, int*, int*,     \
-                               int*, DevParticles<T>&, DevParticles<T>&, void*, \
+                               const BinGeo&, int*, int*, int*, int*,           \
+                               DevParticles<T>&, DevParticles<T>&, void*,       \
                                size_t, hipStream_t);                            \
     template int launch_spread<T>(const DevParticles<T>&, long long,           \
                                   const Geo&, int, int, T*, T*, T*, T*,         \

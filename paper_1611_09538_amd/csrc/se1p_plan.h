@@ -47,7 +47,7 @@ struct se1p_plan {
     // device memory (single allocation, carved)
     void* base = nullptr;
     size_t ws_bytes = 0;
-    int *key_lex = nullptr, *key_blk = nullptr, *slot_lex = nullptr, *slot_blk = nullptr;
+    int *key_lex = nullptr, *slot_lex = nullptr;
     int *cnt_lex = nullptr, *cnt_blk = nullptr;
     int *lex_i[5] = {}, *blk_i[5] = {};   // cx, cy, cz, perm, start
     void *lex_f[7] = {}, *blk_f[7] = {};  // x, y, z, q, tx, ty, tz
