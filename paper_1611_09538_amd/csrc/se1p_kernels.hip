@@ -927,7 +927,6 @@ __device__ __forceinline__ void gather_body(
     const int X0u = bxk * bg.BX + 1;  // array index of the footprint start
     const int Y0u = byk * bg.BY + 1;
     const int Ux = bg.BX + P - 1;
-    const int Uy = bg.BY + P - 1;
     const int ldy = bg.ldy;           // LDS row pitch (see BinGeo)
     const int zl0 = bzk * bg.BZ - P / 2 + 1;  // z index of the union start
     const T h = (T)g.h, a = (T)g.alpha;
@@ -2311,11 +2310,13 @@ int batch_occupancy(int queue, int P, size_t lds, int* blocks_per_cu) {
 SE1P_INST(double)
 SE1P_INST(float)
 
-// Temporary storage the scan needs for n ints.
+// Temporary storage the scan needs for n ints (0 if the query fails; the
+// scan itself then reports the error).
 size_t scan_temp_bytes(long long n) {
     size_t tb = 0;
-    hipcub::DeviceScan::ExclusiveSum(nullptr, tb, (int*)nullptr, (int*)nullptr,
-                                     (int)n, (hipStream_t)0);
+    if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, (int*)nullptr, (int*)nullptr,
+                                         (int)n, (hipStream_t)0) != hipSuccess)
+        return 0;
     return tb;
 }
 
