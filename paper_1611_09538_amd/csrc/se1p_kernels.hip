@@ -1104,8 +1104,9 @@ __global__ __launch_bounds__(64) void gather_kernel(
 // next batch's loads in flight while the current one is processed.  A first
 // pass sets, per lane, one bit per candidate of its quarter within the
 // cut-off; a second pass lets every lane pop its own bits, so the erfc and
-// exp run for in-range pairs only, with most lanes busy.  The four partial
-// sums of a target are added with lane shuffles.
+// exp run for in-range pairs only, with most lanes busy (bits left over
+// carry to the next batch's pass).  The four partial sums of a target are
+// added with lane shuffles.
 // erfc(xi r) / r and the radial field factor q (erfc(xi r)/r +
 // 2 xi/sqrt(pi) exp(-xi^2 r^2)) / r^2 of one pair.  FP64 shares the
 // exponential: erfc(x) = exp(-x^2) erfcx(x) with erfcx from the fitted
