@@ -1122,15 +1122,13 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
 }
 
 // exp(y) for -708 < y <= 0: y = k ln2 + r with |r| <= ln2/2 (Cody-Waite
-// split of ln2), exp(r) by its Taylor series to degree 11 (truncation
-// below 7e-15 relative), scaled by 2^k.
+// split of ln2), exp(r) by its Taylor series to degree 9 (truncation below
+// 7e-12 relative, the size of the erfcx fit's error), scaled by 2^k.
 __device__ __forceinline__ double exp_neg(double y) {
     const double k = rint(y * 1.4426950408889634074);
     double r = fma3(-k, 6.93147180369123816490e-01, y);
     r = fma3(-k, 1.90821492927058770002e-10, r);
-    double p = 1.0 / 39916800.0;                      // 1/11!
-    p = fma3(p, r, 1.0 / 3628800.0);
-    p = fma3(p, r, 1.0 / 362880.0);
+    double p = 1.0 / 362880.0;                        // 1/9!
     p = fma3(p, r, 1.0 / 40320.0);
     p = fma3(p, r, 1.0 / 5040.0);
     p = fma3(p, r, 1.0 / 720.0);
@@ -1151,7 +1149,14 @@ __device__ __forceinline__ void pair_terms<double>(double r2, double xi,
                                                    double xi2, double c_erf,
                                                    double qn, double& ec,
                                                    double& f) {
-    const double rinv = rsqrt(r2);
+    // hardware reciprocal square root and one Newton step (r2 is positive
+    // and normal: distinct particles of a box of size ~1)
+    double rinv = __builtin_amdgcn_rsq(r2);
+    {
+        const double hr = r2 * rinv;
+        const double en = fma(-hr, rinv, 1.0);          // 1 - r2 y^2
+        rinv = fma(0.5 * rinv, en, rinv);
+    }
     const double r = r2 * rinv;
     const double x = fmin(xi * r, kErfcxXmax);
     const double e = exp_neg(-xi2 * r2);
