@@ -1263,15 +1263,21 @@ __device__ __forceinline__ void realspace_body(
         auto process = [&](int n, int slot) {
             // pass 1: one bit per in-range candidate j = kq + 4 i
             unsigned int nmask = 0u;
-            for (int i = 0; 4 * i < n; ++i) {
+            auto test = [&](int i, bool full) {
                 const int j = kq + 4 * i;
                 const int jj = 64 * slot + j;
                 const T dx = xt - cx_[jj], dy = yt - cy_[jj], dz = zt - cz_[jj];
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 // bitwise, not short-circuit: straight-line compares instead
                 // of a branch per candidate (all j < 64 are in the slot)
-                const bool in = (j < n) & (r2 <= rc2) & (r2 > (T)0);
+                const bool in = (full | (j < n)) & (r2 <= rc2) & (r2 > (T)0);
                 nmask |= (unsigned int)in << i;
+            };
+            if (n == 64) {             // a full batch: straight-line code
+#pragma unroll
+                for (int i = 0; i < 16; ++i) test(i, true);
+            } else {
+                for (int i = 0; 4 * i < n; ++i) test(i, false);
             }
             if (!act) nmask = 0u;
             mask |= nmask << 16;
