@@ -24,6 +24,8 @@ Extra fields:
                   FP32 path and the FP64 path at the same parameters
   adaptive_fft    the transform stage against the plain upsampled transform
                   (every k3 slab upsampled) on the same system
+  aft_sweep       the same ratio on the grids of the paper's FFT ratio table
+                  (M = 16 .. 128, s_l = 2 and 4, n_l = 8), beside its values
   se3p_comparison k-space time of SE1P against the triply periodic SE3P on
                   the paper's density-125, xi = 4 timing systems (N = 1e5) at
                   its 1e-5 and 1e-9 parameters, and per particle over its
@@ -209,6 +211,51 @@ def adaptive_extra(se1p, workloads, torch, dev, steps, warmup, case, kspace_ms, 
     return {"adaptive_kspace_ms": kspace_ms, "plain_kspace_ms": plain,
             "speedup": plain / kspace_ms, "n_l_plain": c["M3"] // 2,
             "rel_rms_phi_adaptive_vs_plain": float(d.item())}
+
+
+# The paper's FFT ratio table (plain upsampled over adaptive transform,
+# n_l = 8) for M = 16 .. 128 and s_l = 2, 4, as printed there.
+AFT_TABLE_M = (16, 32, 48, 64, 80, 96, 112, 128)
+AFT_TABLE = {2.0: (0.78, 1.43, 1.77, 2.23, 2.28, 2.51, 2.64, 2.51),
+             4.0: (1.23, 2.43, 3.36, 4.65, 5.06, 5.99, 6.85, 6.30)}
+
+
+def aft_sweep_extra(se1p, workloads, torch, dev, steps, warmup):
+    """Transform-stage time (forward transforms, scaling, inverse transforms)
+    of the plain upsampled FFT over the adaptive one, on the grids of the
+    paper's FFT ratio table: unit box, P = 8, xi = 0.3 M, n_l = 8, s_l = 2
+    and 4.  The plain transform upsamples every k3 slab by s_l; both take
+    the k3 = 0 slab at s0 = max(s_l, 1 + sqrt 2).  M = 112 becomes 108 (the
+    transforms take radices 2, 3, 4, 5).  The stage time does not depend on
+    the particles: 2000 charges, k-space only."""
+    import numpy as np
+    rng = np.random.default_rng(5)
+    box = np.array([1.0, 1.0, 1.0])
+    n = 2000
+    xt = torch.tensor(workloads.uniform_positions(rng, n, box), device=dev)
+    qt = torch.tensor(workloads.neutral_uniform(rng, n), device=dev)
+    phi = torch.empty(n, device=dev, dtype=torch.float64)
+    E = torch.empty((n, 3), device=dev, dtype=torch.float64)
+    U = torch.empty(1, device=dev, dtype=torch.float64)
+    rows = []
+    for s in (2.0, 4.0):
+        for k, Mp in enumerate(AFT_TABLE_M):
+            M = 108 if Mp == 112 else Mp
+            ms = {}
+            for name, nl in (("adaptive", min(8, M // 2)), ("plain", M // 2)):
+                prm = se1p.make_params(box, 0.3 * M, M, 8, nl, s, s0=s, rc=0.0)
+                plan = se1p.Plan(prm, n_max=n)
+                plan.timing_select(["kspace"])
+                plan.timing_enable(True)
+                timed(lambda: plan.eval_into(xt, qt, phi, E, U, flags=se1p.KSPACE),
+                      steps, warmup, torch)
+                st, nc = plan.timing_read()
+                plan.close()
+                ms[name] = st["kspace"] / max(nc, 1)
+            rows.append({"M": M, "s_l": s, "plain_ms": ms["plain"], "adaptive_ms": ms["adaptive"],
+                         "ratio": ms["plain"] / ms["adaptive"], "paper_ratio": AFT_TABLE[s][k]})
+    return {"workload": "unit box, P 8, xi 0.3 M, n_l 8, FP64, transform stage only",
+            "rows": rows}
 
 
 def se3p_extra(se1p, workloads, torch, dev, steps, warmup):
@@ -487,6 +534,9 @@ def main():
             out["adaptive_fft"] = adaptive_extra(se1p, workloads, torch, dev,
                                                  max(5, a.steps // 2), 2, a.case,
                                                  st_ms["kspace"], phi)
+            out["aft_sweep"] = aft_sweep_extra(se1p, workloads, torch, dev,
+                                               max(5, a.steps // 2), 2)
+            print("transform sweep done", file=sys.stderr, flush=True)
         out["fp32"] = fp32_extra(se1p, workloads, torch, dev, max(5, a.steps // 2), 2)
         print("fp32 done", file=sys.stderr, flush=True)
         out["batched"] = batched_extra(se1p, workloads, torch, dev, max(5, a.steps // 2), 2)
