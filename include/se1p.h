@@ -59,7 +59,7 @@ extern "C" {
 #define SE1P_ERR_HIP         -5  /* a HIP runtime call failed */
 #define SE1P_ERR_NOMEM       -6  /* device allocation failed */
 #define SE1P_ERR_TOO_MANY    -7  /* N larger than the plan's n_max */
-#define SE1P_ERR_UNSUPPORTED -8  /* valid request outside what this build supports */
+#define SE1P_ERR_UNSUPPORTED -8  /* valid request outside what this library supports */
 
 /* ---- precision ---------------------------------------------------------- */
 #define SE1P_FP64 0

@@ -12,7 +12,7 @@ scaling, gather) with the oracle's k3 != 0 and k3 = 0 sums at the same xi:
     xy edge (case 1) and a +-1 pair with the free charge on the xy diagonal
     (case 2);
   * the paper's parameter table for N = 120, L = 10, Q = 1 (each row within
-    3x the error the paper reports for it), and this build's parameter recipe
+    3x the error the paper reports for it), and the library's parameter recipe
     of section 4.3 for the same systems (absolute rms error of the k-space
     potential within 50x the tolerance: the estimates are not bounds).
 The grid size M = 38 of the force example is replaced by 40 (the transforms
