@@ -1177,7 +1177,9 @@ __device__ __forceinline__ void pair_terms<float>(float r2, float xi,
                                                   float xi2, float c_erf,
                                                   float qn, float& ec,
                                                   float& f) {
-    const float rinv = rsqrtf(r2);
+    // hardware reciprocal square root: r2 is positive and normal, so the
+    // library's scaling for denormal inputs is not needed
+    const float rinv = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * rinv;
     const float x = fminf(xi * r, (float)kErfcxXmax);
     const float e = __expf(-xi2 * r2);
