@@ -1301,16 +1301,20 @@ __device__ __forceinline__ void realspace_body(
         const int xhi = PXY ? bx1 + R : min(g.M1 - 1, bx1 + R);
         const int nxr = xhi - xlo + 1;
         const int NYP = PXY ? (by1 - by0 + 2 * R) / g.M2 + 2 : 1;
-        // this part's share of the rows: [r0, r1)
+        // this part's rows: r = part + nparts i for i in [0, nrows), so that
+        // every part draws rows from the whole extent of the cut-off sphere
+        // (contiguous row ranges gave the middle parts most of the work,
+        // and with 4 or 8 parts the same part index always fell on the
+        // same XCD)
         const int nrows_all = (bz1 - bz0 + 1 + 2 * R) * nxr * NYP;
-        const int r0 = (int)((long long)nrows_all * part / nparts);
-        const int nrows = (int)((long long)nrows_all * (part + 1) / nparts);
-        int gbase = r0;                // uniform: first row of the current group
+        const int nrows = (nrows_all - part + nparts - 1) / nparts;
+        int gbase = 0;                 // uniform: first row index of the current group
         int gtotal = 0, gdone = 0;     // uniform: candidates of the group, taken
         auto load_rows = [&](int base) {
-            const int r = base + lane;
+            const int ri = base + lane;
+            const int r = part + nparts * ri;
             int rs = 0, re = 0, rsh = 0;
-            if (r < nrows) {
+            if (ri < nrows) {
                 const int rz = PXY ? r / NYP : r;
                 const int czu = bz0 - R + rz / nxr;
                 const int cxu = xlo + rz % nxr;
