@@ -8,6 +8,16 @@ tightly than the approximation error allows against the direct Ewald sums.
 It shares no code with the GPU path; the grid geometry (sizes, padded FFT
 lengths) is passed in explicitly so both sides discretise the same way.
 
+Pins (tests/test_discrete.py, CPU): G_R against a numerical Hankel
+transform of the truncated logarithm and its kappa -> 0 limit; the gridded
+Gaussian of one charge against the mass, mean and variance of a normalised
+Gaussian; the AFT against the discrete Fourier sum written out on a tiny
+grid with per-slab padded sizes; AIFT o AFT against the identity; the gather
+against the transpose of the gridding and its gradient against finite
+differences; the whole k-space potential and field against the direct
+Ewald1P sums in three boxes; the dropped (0, 0) coefficient against keeping
+it.
+
 Readings taken where the paper is silent or garbled (each also listed in the
 design notes):
 
@@ -114,8 +124,12 @@ def spread(geo, x, q):
     return H
 
 
-def scaling(geo, n3, shape):
-    """Scaling factor of eq. scale_1p with G of eq. G_kappa_k on one slab."""
+def scaling(geo, n3, shape, zero_dc=True):
+    """Scaling factor of eq. scale_1p with G of eq. G_kappa_k on one slab.
+
+    ``zero_dc`` sets the (kappa, k3) = (0, 0) coefficient to zero (see the
+    module docstring); with it False the coefficient keeps the value
+    G_R(0) = R^2/4 (1 - 2 log R) of eq. g_zeromod0."""
     n1, n2 = shape
     h, xi, eta = geo.h, geo.xi, geo.eta
     k1 = 2 * np.pi * np.fft.fftfreq(n1, d=h)
@@ -128,26 +142,44 @@ def scaling(geo, n3, shape):
     else:
         G = G_R(np.sqrt(kap2), geo.R)
     S = damp * G
-    if n3 == 0:
+    if n3 == 0 and zero_dc:
         S[0, 0] = 0.0
     return S
 
 
-def kspace_solve(geo, H):
+def aft(geo, H):
+    """Adaptive Fourier transform (Algorithm 2): the 1D FFT along z, then
+    per k3 slab a 2D FFT zero-padded to the slab's size (eq. upsamplings).
+    Returns the list of slab spectra, index k = n3 mod M3."""
+    Hz = np.fft.fft(H, axis=2)                 # step 1
+    slabs = []
+    for k in range(geo.M3):
+        n3 = k if k < geo.M3 // 2 else k - geo.M3
+        slabs.append(np.fft.fft2(Hz[:, :, k], s=geo.slab_size(n3)))
+    return slabs
+
+
+def aift(geo, slabs):
+    """Adaptive inverse transform (Algorithm 3): per slab the normalised 2D
+    IFFT, restricted to the first M~1 x M~2 points, then the normalised
+    inverse 1D FFT along z.  Returns the real grid."""
+    out = np.zeros((geo.Mt[0], geo.Mt[1], geo.M3), dtype=np.complex128)
+    for k, F in enumerate(slabs):
+        out[:, :, k] = np.fft.ifft2(F)[:geo.Mt[0], :geo.Mt[1]]
+    return np.real(np.fft.ifft(out, axis=2))
+
+
+def kspace_solve(geo, H, scale=None):
     """Steps 3-5: AFT (Algorithm 2), scaling, AIFT (Algorithm 3).
     Returns Htilde on the same grid, normalised so that phi^F is
-    4 pi h^3 sum Htilde g."""
-    M3 = geo.M3
-    Hz = np.fft.fft(H, axis=2)                 # step 1 of the AFT
-    out = np.zeros_like(Hz)
-    for k in range(M3):
-        n3 = k if k < M3 // 2 else k - M3
-        size = geo.slab_size(n3)
-        F = np.fft.fft2(Hz[:, :, k], s=size)   # zero-padded 2D FFT
-        F *= scaling(geo, n3, size)
-        back = np.fft.ifft2(F)                 # normalised by 1/(n1 n2)
-        out[:, :, k] = back[:geo.Mt[0], :geo.Mt[1]]   # restrict
-    return np.real(np.fft.ifft(out, axis=2))   # z inverse, 1/M3
+    4 pi h^3 sum Htilde g.  ``scale(geo, n3, shape)`` replaces the scaling
+    of eq. scale_1p when given."""
+    scale = scaling if scale is None else scale
+    slabs = aft(geo, H)
+    for k, F in enumerate(slabs):
+        n3 = k if k < geo.M3 // 2 else k - geo.M3
+        F *= scale(geo, n3, F.shape)
+    return aift(geo, slabs)
 
 
 def gather(geo, Ht, x, field=True):
@@ -172,8 +204,8 @@ def gather(geo, Ht, x, field=True):
     return phi, E
 
 
-def se1p_kspace(geo, x, q, field=True):
-    """phi^F (and E^F) by Algorithm 1."""
+def se1p_kspace(geo, x, q, field=True, scale=None):
+    """phi^F (and E^F) by Algorithm 1 (``scale`` as in kspace_solve)."""
     H = spread(geo, x, q)
-    Ht = kspace_solve(geo, H)
+    Ht = kspace_solve(geo, H, scale=scale)
     return gather(geo, Ht, x, field=field)
