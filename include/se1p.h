@@ -54,7 +54,8 @@ extern "C" {
 #define SE1P_OK               0
 #define SE1P_ERR_ARG         -1  /* NULL pointer, bad size, unknown flag */
 #define SE1P_ERR_PARAM       -2  /* inconsistent method parameters */
-#define SE1P_ERR_NONNEUTRAL  -3  /* |sum q| > 1e-10 sum |q| (section 2.1 needs neutrality) */
+#define SE1P_ERR_NONNEUTRAL  -3  /* |sum q| > tol sum |q|, tol = 1e-10 (FP64) or
+                                    3.8e-6 (FP32) (section 2.1 needs neutrality) */
 #define SE1P_ERR_OUT_OF_BOX  -4  /* x or y outside [0,L1) x [0,L2), or non-finite */
 #define SE1P_ERR_HIP         -5  /* a HIP runtime call failed */
 #define SE1P_ERR_NOMEM       -6  /* device allocation failed */
@@ -142,6 +143,7 @@ typedef struct se1p_plan_info {
     int    gather_chunks;    /* 64-particle chunk slots per gather block */
     int    spread_cz;        /* z cells per gridding chunk */
     int    spread_kp;        /* partial grids written by gridding */
+    long long bin_cells[2];  /* cells of the lex and block orders of binning */
 } se1p_plan_info;
 
 typedef struct se1p_plan se1p_plan;
@@ -209,8 +211,11 @@ int se1p_set_stream(se1p_plan* plan, void* stream);
  * se1p_eval -- one evaluation.
  *   N          number of particles (1 .. n_max).
  *   x          device, N x 3 positions (row-major), FP64/FP32 per plan.
- *   q          device, N charges.  Must sum to zero (within 1e-10 sum |q|)
- *              unless SE1P_NO_NEUTRAL; only checked with SE1P_CHECK_INPUT.
+ *   q          device, N charges.  Must sum to zero (within 1e-10 sum |q|
+ *              for FP64 plans, 32 FP32 epsilons = 3.8e-6 sum |q| for FP32
+ *              plans, the rounding of FP32 charges that are neutral in exact
+ *              arithmetic) unless SE1P_NO_NEUTRAL; only checked with
+ *              SE1P_CHECK_INPUT.
  *   phi        device, N potentials out, or NULL.
  *   efield     device, N x 3 fields out (E = -grad phi), or NULL.
  *   energy     device, one double out: U = 1/2 sum q phi over the requested
@@ -236,6 +241,28 @@ int se1p_eval(se1p_plan* plan, long long N, const void* x, const void* q,
  */
 int se1p_spread(se1p_plan* plan, long long N, const void* x, const void* q,
                 void* grid);
+
+/*
+ * se1p_bin -- the binning stage alone: the counting sort of the particles by
+ * grid cell that the cell lists of the real-space sum (section 2.2, sums
+ * over neighbouring cells within rc) and the gridding and gathering tiles
+ * run on.  A particle's cell is (floor(x/h), floor(y/h), floor(z'/h)) with
+ * z' = z wrapped into [0, L3), each index clamped to the grid.
+ *   lex order    cells numbered (cz, cx, cy), cy fastest;
+ *   block order  cells grouped in blocks of gather_block[0..2] cells (x, y,
+ *                z; se1p_plan_get_info), blocks numbered along a
+ *                serpentine path (z slowest, then x reversed on odd z
+ *                layers, then y reversed on odd rows), cells z-major inside
+ *                a block (z reversed in odd blocks, then x, then y).
+ * Inside a cell particles keep increasing input index, so both orders are
+ * fully determined by x.  Writes (device, each may be NULL):
+ *   lex_perm, blk_perm    N ints: sorted position -> input index;
+ *   lex_start, blk_start  bin_cells[0] + 1 and bin_cells[1] + 1 ints: first
+ *                         sorted position of each cell, then N.
+ * q is read as se1p_eval reads it (its sorted copies are made as well).
+ */
+int se1p_bin(se1p_plan* plan, long long N, const void* x, const void* q,
+             int* lex_perm, int* lex_start, int* blk_perm, int* blk_start);
 
 /*
  * se1p_kspace_solve -- steps 3-5 of Algorithm 1 on a grid from se1p_spread:

@@ -231,12 +231,15 @@ int build_batch(se1p_batch& b) {
     const long long N = std::max<long long>(b.ntot, 1);
     std::vector<Req> req;
     auto add = [&](void** ptr, size_t bytes) { req.push_back({ptr, (bytes + 255) & ~size_t(255)}); };
-    add((void**)&a.key_lex, N * 4);
-    add((void**)&a.key_blk, N * 4);
-    add((void**)&a.slot_lex, N * 4);
-    add((void**)&a.slot_blk, N * 4);
-    add((void**)&a.cnt_lex, (b.ncl + 1) * 4);
-    add((void**)&a.cnt_blk, (b.ncb + 1) * 4);
+    BinBufs& bb = a.bins;
+    bin_sizes(bb, b.ncl, b.ncb);
+    add((void**)&bb.key_lex, N * 4);
+    add((void**)&bb.key_blk, N * 4);
+    add((void**)&bb.slot, N * 4);
+    add((void**)&bb.tmp, N * 4);
+    add((void**)&bb.cnt_lex, (bb.ncl + 1) * 4);
+    add((void**)&bb.cnt_blk, (bb.ncb + 1) * 4);
+    add((void**)&bb.tsum, ((size_t)bb.ntl + bb.ntb) * 4);
     DevParticles<T>* dp[2] = {&a.lex, &a.blk};
     for (DevParticles<T>* d : dp) {
         add((void**)&d->x, N * es);
@@ -253,8 +256,6 @@ int build_batch(se1p_batch& b) {
     }
     add((void**)&a.lex.start, (b.ncl + 1) * 4);
     add((void**)&a.blk.start, (b.ncb + 1) * 4);
-    a.scan_bytes = std::max(scan_temp_bytes(b.ncl + 1), scan_temp_bytes(b.ncb + 1)) + 256;
-    add(&a.scan_tmp, a.scan_bytes);
     add((void**)&a.wz, (size_t)N * P * es);
     add((void**)&a.wxp, (size_t)N * PW * es);
     add((void**)&a.wyq, (size_t)N * PW * es);

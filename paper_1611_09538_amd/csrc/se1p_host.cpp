@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -238,8 +239,8 @@ void choose_spread(se1p_plan& pl) {
 template <typename T>
 DevParticles<T> particles(const se1p_plan& pl, bool lex) {
     DevParticles<T> d;
-    void* const* f = lex ? pl.lex_f : pl.blk_f;
-    int* const* i = lex ? pl.lex_i : pl.blk_i;
+    void* const* f = lex ? pl.w.lex_f : pl.w.blk_f;
+    int* const* i = lex ? pl.w.lex_i : pl.w.blk_i;
     d.x = (T*)f[0]; d.y = (T*)f[1]; d.z = (T*)f[2]; d.q = (T*)f[3];
     d.tx = (T*)f[4]; d.ty = (T*)f[5]; d.tz = (T*)f[6];
     d.cx = i[0]; d.cy = i[1]; d.cz = i[2]; d.perm = i[3]; d.start = i[4];
@@ -396,72 +397,106 @@ void se1p::plan_tables(const se1p_plan& pl, std::vector<double>& twd,
 
 namespace {
 
+// Sequential carving of device memory: each buffer starts on a 256-byte
+// boundary after the previous one.  Pure address arithmetic (no host or
+// device allocation), so the same layout can be placed in any buffer.
+struct Carver {
+    uintptr_t base, off = 0;
+    explicit Carver(uintptr_t b) : base(b) {}
+    template <typename P> void take(P** ptr, size_t bytes) {
+        *ptr = (P*)(base + off);
+        off += (bytes + 255) & ~size_t(255);
+    }
+    size_t used() const { return off; }
+};
+
+}  // namespace
+
+// Lays out the per-call scratch of an evaluation of N particles at base
+// (the plan's own workspace, or the static scratch array) and returns its
+// size in bytes.  Sizes depend on the plan's geometry and on N only.
+size_t se1p::layout_scratch(const se1p_plan& pl, long long n, PlanScratch& w,
+                            uintptr_t base, bool ik) {
+    const se1p_params& p = pl.prm;
+    const size_t cs = 2 * pl.es;
+    const long long N = std::max<long long>(n, 1);
+    Carver c(base);
+    BinBufs& bb = w.bins;
+    bin_sizes(bb, pl.bg.ncell_lex, pl.bg.ncell_blk);
+    c.take(&bb.key_lex, N * 4);
+    c.take(&bb.key_blk, N * 4);
+    c.take(&bb.slot, N * 4);
+    c.take(&bb.tmp, N * 4);
+    c.take(&bb.cnt_lex, (bb.ncl + 1) * 4);
+    c.take(&bb.cnt_blk, (bb.ncb + 1) * 4);
+    c.take(&bb.tsum, ((size_t)bb.ntl + bb.ntb) * 4);
+    for (int k = 0; k < 4; ++k) { c.take(&w.lex_i[k], N * 4); c.take(&w.blk_i[k], N * 4); }
+    c.take(&w.lex_i[4], (pl.bg.ncell_lex + 1) * 4);
+    c.take(&w.blk_i[4], (pl.bg.ncell_blk + 1) * 4);
+    for (int k = 0; k < 7; ++k) { c.take(&w.lex_f[k], N * pl.es); c.take(&w.blk_f[k], N * pl.es); }
+    const int PW = p.P + 2 * weight_pad((int)pl.es);
+    c.take(&w.wz, (size_t)N * p.P * pl.es);
+    c.take(&w.wxp, (size_t)N * PW * pl.es);
+    c.take(&w.wyq, (size_t)N * PW * pl.es);
+    c.take(&w.Hpart, (size_t)pl.KP * pl.pstride * pl.es);
+    c.take(&w.Fz, (size_t)pl.nslab * pl.gf.ncol * cs);
+    if (pl.periodic3) {
+        c.take(&w.Hper, (size_t)p.M3 * pl.gf.ncol * pl.es);
+        c.take(&w.Htp, (size_t)p.M3 * pl.gf.ncol * pl.es);
+    } else {
+        w.Hper = w.Htp = nullptr;
+    }
+    c.take(&w.G, (size_t)pl.slab_elems * cs);
+    c.take(&w.Ht, (size_t)(pl.pstride + 64) * pl.es);   // rows are read in halves
+    if (!pl.periodic3 && ik) {
+        c.take(&w.Gk, 3 * (size_t)pl.slab_elems * cs);
+        c.take(&w.Htk, 3 * (size_t)(pl.pstride + 64) * pl.es);
+    } else {
+        w.Gk = w.Htk = nullptr;
+    }
+    c.take(&w.phiF, N * pl.es);
+    c.take(&w.EF, 3 * N * pl.es);
+    // Real-space work units: 16-target chunks, each split into rs_parts
+    // parts so that the launch has several units per resident wave slot
+    // (1024 SIMDs x 4 waves) and the last round is short.
+    const long long nchunks = (N + 15) / 16;
+    w.rs_parts = (int)std::min<long long>(8, std::max<long long>(1, (32768 + nchunks - 1) / nchunks));
+    c.take(&w.phiR, (size_t)w.rs_parts * N * pl.es);
+    c.take(&w.ER, 3 * (size_t)w.rs_parts * N * pl.es);
+    w.nblk_comb = (int)((N + 255) / 256);
+    c.take(&w.partials, (size_t)w.nblk_comb * 8);
+    c.take(&w.flag, 256);
+    c.take(&w.qsum, 256);
+    return c.used();
+}
+
+namespace {
+
 int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
     int rc0 = plan_geometry(pl, p, n_max);
     if (rc0) return rc0;
     const Geo& g = pl.g;
     const size_t cs = 2 * pl.es;
 
-    // ---- workspace layout ----
-    const long long N = std::max<long long>(n_max, 1);
-    std::vector<std::pair<void**, size_t>> req;
-    auto add = [&](void** ptr, size_t bytes) { req.push_back({ptr, (bytes + 255) & ~size_t(255)}); };
-    add((void**)&pl.key_lex, N * 4);
-    add((void**)&pl.slot_lex, N * 4);
-    add((void**)&pl.cnt_lex, (pl.bg.ncell_lex + 1) * 4);
-    add((void**)&pl.cnt_blk, (pl.bg.ncell_blk + 1) * 4);
-    for (int k = 0; k < 4; ++k) { add((void**)&pl.lex_i[k], N * 4); add((void**)&pl.blk_i[k], N * 4); }
-    add((void**)&pl.lex_i[4], (pl.bg.ncell_lex + 1) * 4);
-    add((void**)&pl.blk_i[4], (pl.bg.ncell_blk + 1) * 4);
-    for (int k = 0; k < 7; ++k) { add(&pl.lex_f[k], N * pl.es); add(&pl.blk_f[k], N * pl.es); }
-    pl.scan_bytes = std::max(scan_temp_bytes(pl.bg.ncell_lex + 1),
-                             scan_temp_bytes(pl.bg.ncell_blk + 1)) + 256;
-    add(&pl.scan_tmp, pl.scan_bytes);
-    const int PW = p.P + 2 * weight_pad((int)pl.es);
-    add(&pl.wz, (size_t)N * p.P * pl.es);
-    add(&pl.wxp, (size_t)N * PW * pl.es);
-    add(&pl.wyq, (size_t)N * PW * pl.es);
+    // ---- workspace: tables, then the plan's own scratch for n_max ----
     pl.pstride = (long long)p.M3 * g.ncol;
-    add(&pl.Hpart, (size_t)pl.KP * pl.pstride * pl.es);
-    add(&pl.Fz, (size_t)pl.nslab * pl.gf.ncol * cs);
-    if (pl.periodic3) {
-        add(&pl.Hper, (size_t)p.M3 * pl.gf.ncol * pl.es);
-        add(&pl.Htp, (size_t)p.M3 * pl.gf.ncol * pl.es);
-    }
-    add(&pl.G, (size_t)pl.slab_elems * cs);
-    add(&pl.Ht, (size_t)(pl.pstride + 64) * pl.es);   // rows are read in halves
-    if (!pl.periodic3) {
-        add(&pl.Gk, 3 * (size_t)pl.slab_elems * cs);
-        add(&pl.Htk, 3 * (size_t)(pl.pstride + 64) * pl.es);
-    }
-    add(&pl.S0, (size_t)pl.n0[0] * pl.n0[1] * pl.es);
-    add(&pl.tw, (size_t)pl.tw_elems * cs);
-    add((void**)&pl.d_slabs, pl.slabs.size() * sizeof(SlabDesc));
-    add(&pl.phiF, N * pl.es);
-    add(&pl.EF, 3 * N * pl.es);
-    // Real-space work units: 16-target chunks, each split into rs_parts
-    // parts so that the launch has several units per resident wave slot
-    // (1024 SIMDs x 4 waves) and the last round is short.
-    {
-        const long long nchunks = (N + 15) / 16;
-        pl.rs_parts = (int)std::min<long long>(8, std::max<long long>(1, (32768 + nchunks - 1) / nchunks));
-    }
-    add(&pl.phiR, (size_t)pl.rs_parts * N * pl.es);
-    add(&pl.ER, 3 * (size_t)pl.rs_parts * N * pl.es);
-    pl.nblk_comb = (int)((N + 255) / 256);
-    add((void**)&pl.partials, (size_t)pl.nblk_comb * 8);
-    add((void**)&pl.flag, 256);
-    add((void**)&pl.qsum, 256);
-    size_t total = 0;
-    for (auto& r : req) total += r.second;
+    Carver tables(0);
+    tables.take(&pl.S0, (size_t)pl.n0[0] * pl.n0[1] * pl.es);
+    tables.take(&pl.tw, (size_t)pl.tw_elems * cs);
+    tables.take((void**)&pl.d_slabs, pl.slabs.size() * sizeof(SlabDesc));
+    const size_t tb = tables.used();
+    const size_t total = tb + layout_scratch(pl, n_max, pl.w, 0);
     pl.ws_bytes = total;
     if (hipMalloc(&pl.base, total) != hipSuccess) {
         pl.base = nullptr;
         (void)hipGetLastError();
         return SE1P_ERR_NOMEM;
     }
-    char* cur = (char*)pl.base;
-    for (auto& r : req) { *r.first = cur; cur += r.second; }
+    const uintptr_t b0 = (uintptr_t)pl.base;
+    pl.S0 = (void*)(b0 + (uintptr_t)pl.S0);
+    pl.tw = (void*)(b0 + (uintptr_t)pl.tw);
+    pl.d_slabs = (SlabDesc*)(b0 + (uintptr_t)pl.d_slabs);
+    layout_scratch(pl, n_max, pl.w, b0 + tb);
 
     // ---- tables: twiddles, slab descriptors, FP64 scaling of slab 0 ----
     std::vector<double> twd, s0;
@@ -485,17 +520,15 @@ int build_plan(se1p_plan& pl, const se1p_params& p, long long n_max) {
 template <typename T>
 int run_bin(se1p_plan& pl, long long N, const void* x, const void* q) {
     DevParticles<T> lex = particles<T>(pl, true), blk = particles<T>(pl, false);
-    return launch_bin<T>((const T*)x, (const T*)q, N, pl.g, pl.bg, pl.key_lex,
-                         pl.slot_lex, pl.cnt_lex, pl.cnt_blk, lex, blk,
-                         pl.scan_tmp, pl.scan_bytes,
+    return launch_bin<T>((const T*)x, (const T*)q, N, pl.g, pl.bg, pl.w.bins, lex, blk,
                          pl.stream);
 }
 
 template <typename T>
 int run_spread(se1p_plan& pl, long long N) {
     DevParticles<T> lex = particles<T>(pl, true);
-    return launch_spread<T>(lex, N, pl.g, pl.CZ, pl.KP, (T*)pl.wz, (T*)pl.wxp,
-                            (T*)pl.wyq, (T*)pl.Hpart, pl.pstride, pl.stream);
+    return launch_spread<T>(lex, N, pl.g, pl.CZ, pl.KP, (T*)pl.w.wz, (T*)pl.w.wxp,
+                            (T*)pl.w.wyq, (T*)pl.w.Hpart, pl.pstride, pl.stream);
 }
 
 template <typename T>
@@ -505,7 +538,7 @@ int run_kspace(se1p_plan& pl, const T* Hin, int KP, T in_scale, T out_scale,
                             in_scale, pl.gf, pl.nslab,
                             pl.d_slabs, pl.slabs.data(), pl.dz,
                             (const cplx<T>*)pl.tw, (const T*)pl.S0,
-                            (cplx<T>*)pl.Fz, (cplx<T>*)pl.G, out_scale, Ht,
+                            (cplx<T>*)pl.w.Fz, (cplx<T>*)pl.w.G, out_scale, Ht,
                             pl.stream);
 }
 
@@ -525,36 +558,36 @@ int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
         if (pl.periodic3) {
             // fold the gridded values onto the periodic grid, transform,
             // and spread the result back over the gather's extended grid
-            if ((rc = launch_fold<T>((const T*)pl.Hpart, pl.KP, pl.pstride, pl.g, pl.gf,
-                                     (T*)pl.Hper, pl.stream))) return rc;
-            if ((rc = run_kspace<T>(pl, (const T*)pl.Hper, 1, (T)1, (T)1, (T*)pl.Htp))) return rc;
-            if ((rc = launch_unfold<T>((const T*)pl.Htp, pl.g, pl.gf, (T*)pl.Ht, pl.stream)))
+            if ((rc = launch_fold<T>((const T*)pl.w.Hpart, pl.KP, pl.pstride, pl.g, pl.gf,
+                                     (T*)pl.w.Hper, pl.stream))) return rc;
+            if ((rc = run_kspace<T>(pl, (const T*)pl.w.Hper, 1, (T)1, (T)1, (T*)pl.w.Htp))) return rc;
+            if ((rc = launch_unfold<T>((const T*)pl.w.Htp, pl.g, pl.gf, (T*)pl.w.Ht, pl.stream)))
                 return rc;
         } else if (flags & SE1P_FIELD_IK) {
-            if ((rc = launch_kspace_ik<T>((const T*)pl.Hpart, pl.KP, pl.pstride, pl.g,
+            if ((rc = launch_kspace_ik<T>((const T*)pl.w.Hpart, pl.KP, pl.pstride, pl.g,
                                           pl.nslab, pl.d_slabs, pl.slabs.data(), pl.dz,
                                           (const cplx<T>*)pl.tw, (const T*)pl.S0,
-                                          (cplx<T>*)pl.Fz, (cplx<T>*)pl.G,
-                                          (cplx<T>*)pl.Gk, pl.slab_elems, (T*)pl.Ht,
-                                          (T*)pl.Htk, pl.pstride + 64, pl.stream)))
+                                          (cplx<T>*)pl.w.Fz, (cplx<T>*)pl.w.G,
+                                          (cplx<T>*)pl.w.Gk, pl.slab_elems, (T*)pl.w.Ht,
+                                          (T*)pl.w.Htk, pl.pstride + 64, pl.stream)))
                 return rc;
         } else {
-            if ((rc = run_kspace<T>(pl, (const T*)pl.Hpart, pl.KP, (T)1, (T)1, (T*)pl.Ht))) return rc;
+            if ((rc = run_kspace<T>(pl, (const T*)pl.w.Hpart, pl.KP, (T)1, (T)1, (T*)pl.w.Ht))) return rc;
         }
         tmark(pl, 3);
         DevParticles<T> blk = particles<T>(pl, false);
         if (flags & SE1P_FIELD_IK) {
             // the potential and each field component from its own grid
-            if ((rc = launch_gather_phi<T>((const T*)pl.Ht, blk, pl.g, pl.bg, (T)1,
-                                           (T*)pl.phiF, 1, pl.stream)))
+            if ((rc = launch_gather_phi<T>((const T*)pl.w.Ht, blk, pl.g, pl.bg, (T)1,
+                                           (T*)pl.w.phiF, 1, pl.stream)))
                 return rc;
             for (int d = 0; d < 3; ++d)
-                if ((rc = launch_gather_phi<T>((const T*)pl.Htk + d * (pl.pstride + 64), blk,
-                                               pl.g, pl.bg, (T)1, (T*)pl.EF + d, 3,
+                if ((rc = launch_gather_phi<T>((const T*)pl.w.Htk + d * (pl.pstride + 64), blk,
+                                               pl.g, pl.bg, (T)1, (T*)pl.w.EF + d, 3,
                                                pl.stream)))
                     return rc;
-        } else if ((rc = launch_gather<T>((const T*)pl.Ht, blk, N, pl.g, pl.bg, (T)1,
-                                          (T*)pl.phiF, (T*)pl.EF, pl.stream))) {
+        } else if ((rc = launch_gather<T>((const T*)pl.w.Ht, blk, N, pl.g, pl.bg, (T)1,
+                                          (T*)pl.w.phiF, (T*)pl.w.EF, pl.stream))) {
             return rc;
         }
         mask |= 2 | 4 | 8;
@@ -567,7 +600,7 @@ int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
         DevParticles<T> lex = particles<T>(pl, true);
         DevParticles<T> blk = particles<T>(pl, false);
         if ((rc = launch_realspace<T>(lex, blk, N, pl.g, pl.bg, pl.prm.xi, pl.prm.rc,
-                                      pl.rs_parts, pl.periodic3, (T*)pl.phiR, (T*)pl.ER,
+                                      pl.w.rs_parts, pl.periodic3, (T*)pl.w.phiR, (T*)pl.w.ER,
                                       pl.stream)))
             return rc;
         mask |= 16;
@@ -577,9 +610,9 @@ int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
     tmark(pl, 5);
     const double self_c = 2.0 * pl.prm.xi / std::sqrt(kPi);
     const int nb = (int)((N + 255) / 256);
-    rc = launch_combine<T>(N, (const T*)q, (const T*)pl.phiF, (const T*)pl.EF,
-                           (const T*)pl.phiR, (const T*)pl.ER, pl.rs_parts, self_c, comp,
-                           (T*)phi, (T*)efield, pl.partials, nb, energy,
+    rc = launch_combine<T>(N, (const T*)q, (const T*)pl.w.phiF, (const T*)pl.w.EF,
+                           (const T*)pl.w.phiR, (const T*)pl.w.ER, pl.w.rs_parts, self_c, comp,
+                           (T*)phi, (T*)efield, pl.w.partials, nb, energy,
                            pl.stream);
     if (rc) return rc;
     mask |= 32;
@@ -591,31 +624,71 @@ int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
     return SE1P_OK;
 }
 
+// Relative neutrality bar |sum q| <= tol sum |q| of SE1P_CHECK_INPUT.  FP64
+// charges: 1e-10.  FP32 charges: 32 FP32 epsilons (3.8e-6), since charges
+// that are neutral in exact arithmetic leave up to eps/2 sum |q| from the
+// rounding to FP32 alone, plus about eps log2(N) sum |q| when the shift to
+// zero sum was itself computed in FP32 with a tree reduction.
+double neutral_tol(int prec) {
+    return prec == SE1P_FP32 ? 32.0 * 1.1920928955078125e-7 : 1e-10;
+}
+
 template <typename T>
 int run_check(se1p_plan& pl, long long N, const void* x, const void* q,
               bool neutral) {
-    if (hipMemsetAsync(pl.flag, 0, 4, pl.stream) != hipSuccess) return SE1P_ERR_HIP;
-    if (hipMemsetAsync(pl.qsum, 0, 16, pl.stream) != hipSuccess) return SE1P_ERR_HIP;
+    // cleared by a kernel: the flag and the two sums are 1 + 4 ints
+    if (launch_fill_int(pl.w.flag, 1, 0, pl.stream)) return SE1P_ERR_HIP;
+    if (launch_fill_int((int*)pl.w.qsum, 4, 0, pl.stream)) return SE1P_ERR_HIP;
     int rc = launch_check<T>((const T*)x, (const T*)q, N, pl.prm.box[0],
-                             pl.prm.box[1], pl.flag, pl.qsum, pl.stream);
+                             pl.prm.box[1], pl.w.flag, pl.w.qsum, pl.stream);
     if (rc) return rc;
     int hflag = 0;
     double hq[2] = {0, 0};
-    if (hipMemcpyAsync(&hflag, pl.flag, 4, hipMemcpyDeviceToHost, pl.stream) != hipSuccess)
+    if (hipMemcpyAsync(&hflag, pl.w.flag, 4, hipMemcpyDeviceToHost, pl.stream) != hipSuccess)
         return SE1P_ERR_HIP;
-    if (hipMemcpyAsync(hq, pl.qsum, 16, hipMemcpyDeviceToHost, pl.stream) != hipSuccess)
+    if (hipMemcpyAsync(hq, pl.w.qsum, 16, hipMemcpyDeviceToHost, pl.stream) != hipSuccess)
         return SE1P_ERR_HIP;
     if (hipStreamSynchronize(pl.stream) != hipSuccess) return SE1P_ERR_HIP;
     if (hflag) return SE1P_ERR_OUT_OF_BOX;
-    if (neutral && std::fabs(hq[0]) > 1e-10 * hq[1]) return SE1P_ERR_NONNEUTRAL;
+    if (neutral && std::fabs(hq[0]) > neutral_tol(pl.prec) * hq[1]) return SE1P_ERR_NONNEUTRAL;
     return SE1P_OK;
 }
+
+}  // namespace
+
+namespace se1p {
 
 int set_device(const se1p_plan* pl) {
     return hipSetDevice(pl->device) == hipSuccess ? SE1P_OK : SE1P_ERR_HIP;
 }
 
-}  // namespace
+// Host-side argument checks of se1p_eval and se1p_eval_noalloc.
+int eval_args(const se1p_plan* pl, long long N, const void* x, const void* q,
+              unsigned flags) {
+    if (!pl || !x || !q) return SE1P_ERR_ARG;
+    if (flags & ~(SE1P_ALL | SE1P_CHECK_INPUT | SE1P_NO_NEUTRAL | SE1P_FIELD_IK))
+        return SE1P_ERR_ARG;
+    if ((flags & SE1P_FIELD_IK) && pl->periodic3) return SE1P_ERR_UNSUPPORTED;
+    if ((flags & SE1P_ALL) == 0) return SE1P_ERR_ARG;
+    if (N < 1 || N > (1LL << 30)) return SE1P_ERR_ARG;
+    if ((flags & SE1P_REAL) && !(pl->prm.rc > 0.0)) return SE1P_ERR_PARAM;
+    return SE1P_OK;
+}
+
+int eval_body(se1p_plan* pl, long long N, const void* x, const void* q,
+              void* phi, void* efield, double* energy, unsigned flags) {
+    if (flags & SE1P_CHECK_INPUT) {
+        const bool neutral = !(flags & SE1P_NO_NEUTRAL);
+        int rc = (pl->prec == SE1P_FP64) ? run_check<double>(*pl, N, x, q, neutral)
+                                         : run_check<float>(*pl, N, x, q, neutral);
+        if (rc) return rc;
+    }
+    if (pl->prec == SE1P_FP64)
+        return run_eval<double>(*pl, N, x, q, phi, efield, energy, flags);
+    return run_eval<float>(*pl, N, x, q, phi, efield, energy, flags);
+}
+
+}  // namespace se1p
 
 extern "C" {
 
@@ -836,6 +909,8 @@ int se1p_plan_get_info(const se1p_plan* pl, se1p_plan_info* info) {
     info->gather_chunks = pl->bg.CH;
     info->spread_cz = pl->CZ;
     info->spread_kp = pl->KP;
+    info->bin_cells[0] = pl->bg.ncell_lex;
+    info->bin_cells[1] = pl->bg.ncell_blk;
     return SE1P_OK;
 }
 
@@ -847,24 +922,11 @@ int se1p_set_stream(se1p_plan* plan, void* stream) {
 
 int se1p_eval(se1p_plan* pl, long long N, const void* x, const void* q,
               void* phi, void* efield, double* energy, unsigned flags) {
-    if (!pl || !x || !q) return SE1P_ERR_ARG;
-    if (flags & ~(SE1P_ALL | SE1P_CHECK_INPUT | SE1P_NO_NEUTRAL | SE1P_FIELD_IK))
-        return SE1P_ERR_ARG;
-    if ((flags & SE1P_FIELD_IK) && pl->periodic3) return SE1P_ERR_UNSUPPORTED;
-    if ((flags & SE1P_ALL) == 0) return SE1P_ERR_ARG;
-    if (N < 1) return SE1P_ERR_ARG;
+    int rc = eval_args(pl, N, x, q, flags);
+    if (rc) return rc;
     if (N > pl->n_max) return SE1P_ERR_TOO_MANY;
-    if ((flags & SE1P_REAL) && !(pl->prm.rc > 0.0)) return SE1P_ERR_PARAM;
     if (set_device(pl)) return SE1P_ERR_HIP;
-    if (flags & SE1P_CHECK_INPUT) {
-        const bool neutral = !(flags & SE1P_NO_NEUTRAL);
-        int rc = (pl->prec == SE1P_FP64) ? run_check<double>(*pl, N, x, q, neutral)
-                                         : run_check<float>(*pl, N, x, q, neutral);
-        if (rc) return rc;
-    }
-    if (pl->prec == SE1P_FP64)
-        return run_eval<double>(*pl, N, x, q, phi, efield, energy, flags);
-    return run_eval<float>(*pl, N, x, q, phi, efield, energy, flags);
+    return eval_body(pl, N, x, q, phi, efield, energy, flags);
 }
 
 int se1p_spread(se1p_plan* pl, long long N, const void* x, const void* q,
@@ -879,13 +941,35 @@ int se1p_spread(se1p_plan* pl, long long N, const void* x, const void* q,
     if (pl->prec == SE1P_FP64) {
         if ((rc = run_bin<double>(*pl, N, x, q))) return rc;
         if ((rc = run_spread<double>(*pl, N))) return rc;
-        return launch_reduce_partials<double>((const double*)pl->Hpart, pl->KP, n, n,
+        return launch_reduce_partials<double>((const double*)pl->w.Hpart, pl->KP, n, n,
                                               pl->cg, (double*)grid, pl->stream);
     }
     if ((rc = run_bin<float>(*pl, N, x, q))) return rc;
     if ((rc = run_spread<float>(*pl, N))) return rc;
-    return launch_reduce_partials<float>((const float*)pl->Hpart, pl->KP, n, n,
+    return launch_reduce_partials<float>((const float*)pl->w.Hpart, pl->KP, n, n,
                                          (float)pl->cg, (float*)grid, pl->stream);
+}
+
+int se1p_bin(se1p_plan* pl, long long N, const void* x, const void* q,
+             int* lex_perm, int* lex_start, int* blk_perm, int* blk_start) {
+    if (!pl || !x || !q) return SE1P_ERR_ARG;
+    if (N < 1) return SE1P_ERR_ARG;
+    if (N > pl->n_max) return SE1P_ERR_TOO_MANY;
+    if (set_device(pl)) return SE1P_ERR_HIP;
+    const int rc = pl->prec == SE1P_FP64 ? run_bin<double>(*pl, N, x, q)
+                                         : run_bin<float>(*pl, N, x, q);
+    if (rc) return rc;
+    const size_t np = (size_t)N * 4;
+    const struct { int* dst; const int* src; size_t bytes; } cp[4] = {
+        {lex_perm, pl->w.lex_i[3], np},
+        {lex_start, pl->w.lex_i[4], (size_t)(pl->bg.ncell_lex + 1) * 4},
+        {blk_perm, pl->w.blk_i[3], np},
+        {blk_start, pl->w.blk_i[4], (size_t)(pl->bg.ncell_blk + 1) * 4}};
+    for (const auto& c : cp)
+        if (c.dst && hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice,
+                                    pl->stream) != hipSuccess)
+            return SE1P_ERR_HIP;
+    return SE1P_OK;
 }
 
 int se1p_kspace_solve(se1p_plan* pl, const void* grid_in, void* grid_out) {
@@ -914,20 +998,20 @@ int se1p_gather(se1p_plan* pl, long long N, const void* x, const void* grid,
     int rc;
     // The gather reads grid rows in halves and may touch one element past
     // the last row; it runs on the plan's padded copy of the caller's grid.
-    if (hipMemcpyAsync(pl->Ht, grid, (size_t)pl->pstride * pl->es,
+    if (hipMemcpyAsync(pl->w.Ht, grid, (size_t)pl->pstride * pl->es,
                        hipMemcpyDeviceToDevice, pl->stream) != hipSuccess)
         return SE1P_ERR_HIP;
     // binning sorts charges along with positions; the gather does not use
     // them, so the plan's scratch phiF stands in for q.
     if (pl->prec == SE1P_FP64) {
-        if ((rc = run_bin<double>(*pl, N, x, pl->phiF))) return rc;
+        if ((rc = run_bin<double>(*pl, N, x, pl->w.phiF))) return rc;
         DevParticles<double> blk = particles<double>(*pl, false);
-        return launch_gather<double>((const double*)pl->Ht, blk, N, pl->g, pl->bg, sc,
+        return launch_gather<double>((const double*)pl->w.Ht, blk, N, pl->g, pl->bg, sc,
                                      (double*)phi, (double*)efield, pl->stream);
     }
-    if ((rc = run_bin<float>(*pl, N, x, pl->phiF))) return rc;
+    if ((rc = run_bin<float>(*pl, N, x, pl->w.phiF))) return rc;
     DevParticles<float> blk = particles<float>(*pl, false);
-    return launch_gather<float>((const float*)pl->Ht, blk, N, pl->g, pl->bg, (float)sc,
+    return launch_gather<float>((const float*)pl->w.Ht, blk, N, pl->g, pl->bg, (float)sc,
                                 (float*)phi, (float*)efield, pl->stream);
 }
 

@@ -84,11 +84,36 @@ struct DevParticles {        // sorted copies of the particles in one order
     int* start;              // cell starts, size ncell + 1
 };
 
+// Counting sort scratch.  Cell counts of both orders are scanned into the
+// cell starts by hand-written reduce-then-scan kernels: one pass sums each
+// tile of kScanTile counts, the next scans every tile with the sum of the
+// tiles before it as offset (integer sums, so the starts do not depend on
+// the order in which anything ran).
+constexpr int kScanItems = 16;                 // counts per thread
+constexpr int kScanTile = 256 * kScanItems;    // counts per workgroup
+inline int scan_tiles(long long n) { return (int)((n + kScanTile - 1) / kScanTile); }
+
+struct BinBufs {
+    int* key_lex; int* key_blk;   // N: cell of each particle in both orders
+    int* slot;                    // N: arrival slot in its lex cell
+    int* tmp;                     // N: lex order by arrival (before ranking)
+    int* cnt_lex; int* cnt_blk;   // ncl + 1, ncb + 1 cell counts
+    int* tsum;                    // ntl + ntb particles per scan tile
+    long long ncl, ncb;           // cells in the lex and block orders
+    int ntl, ntb;                 // scan tiles over ncl + 1 and ncb + 1 entries
+};
+// Sizes of the per-cell parts of BinBufs for ncl lex and ncb block cells.
+inline void bin_sizes(BinBufs& b, long long ncl, long long ncb) {
+    b.ncl = ncl;
+    b.ncb = ncb;
+    b.ntl = scan_tiles(ncl + 1);
+    b.ntb = scan_tiles(ncb + 1);
+}
+
 template <typename T>
 int launch_bin(const T* x_in, const T* q_in, long long N, const Geo& g,
-               const BinGeo& bg, int* key_lex, int* slot_lex, int* cnt_lex,
-               int* cnt_blk, DevParticles<T>& lex, DevParticles<T>& blk,
-               void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s);
+               const BinGeo& bg, const BinBufs& b, DevParticles<T>& lex,
+               DevParticles<T>& blk, hipStream_t s);
 
 template <typename T>
 int launch_spread(const DevParticles<T>& lex, long long N, const Geo& g,
@@ -209,10 +234,8 @@ struct BatchArgs {
     long long ntot;
     const int* sys_of;          // packed particle -> system
     long long ncl, ncb;         // total lex / block cells
-    int* key_lex; int* key_blk; int* slot_lex; int* slot_blk;
-    int* cnt_lex; int* cnt_blk;
+    BinBufs bins;               // counting sort over the packed cells
     DevParticles<T> lex, blk;   // packed, start = global cell starts
-    void* scan_tmp; size_t scan_bytes;
     T* wz; T* wxp; T* wyq;
     const cplx<T>* tw;
     T* phiF; T* EF; T* phiR; T* ER;

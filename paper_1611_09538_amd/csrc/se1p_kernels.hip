@@ -20,7 +20,6 @@
 // The Gaussian normalisation and all transform normalisations are folded
 // into the scaling factors, so spread and gather use exp(-alpha d^2).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include "erfcx_poly.h"
 #include "se1p_internal.h"
@@ -258,97 +257,171 @@ __device__ __forceinline__ void cell_keys(const T* __restrict__ xin, long long i
     kb = b * bg.cpb + (izs * bg.BX + ix) * bg.BY + iy;
 }
 
-// Lex cell key of each particle and its slot in the cell (counting sort).
+// Records the cell keys of particle i, takes its arrival slot in its lex
+// cell and counts it in the cells of both orders.
+__device__ __forceinline__ void count_keys(long long i, int kl, int kb,
+                                           const BinBufs& b) {
+    b.key_lex[i] = kl;
+    b.key_blk[i] = kb;
+    b.slot[i] = atomicAdd(&b.cnt_lex[kl], 1);
+    atomicAdd(&b.cnt_blk[kb], 1);
+}
+
 template <typename T>
 __global__ void bin_keys_kernel(const T* __restrict__ xin, long long N, Geo g,
-                                int* __restrict__ key_lex,
-                                int* __restrict__ slot_lex,
-                                int* __restrict__ cnt_lex) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+                                BinGeo bg, BinBufs b) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    T zw;
-    int cx, cy, cz;
-    cell_of<T>(xin[3 * i], xin[3 * i + 1], xin[3 * i + 2], g, zw, cx, cy, cz);
-    const int kl = (cz * g.M1 + cx) * g.M2 + cy;
-    key_lex[i] = kl;
-    slot_lex[i] = atomicAdd(&cnt_lex[kl], 1);
+    int kl, kb;
+    cell_keys<T>(xin, i, g, bg, kl, kb);
+    count_keys(i, kl, kb, b);
 }
 
-// The block order numbers the same cells as the lex order: lex cell of the
-// block-order cell kb (the inverse of the block key of cell_keys), or -1
-// for the cells of partial blocks beyond the grid.
-__device__ __forceinline__ long long lex_of_blk(long long kb, const Geo& g,
-                                                const BinGeo& bg) {
-    const int b = (int)(kb / bg.cpb);
-    const int r = (int)(kb - (long long)b * bg.cpb);
-    const int izs = r / (bg.BX * bg.BY);
-    const int ix = (r / bg.BY) % bg.BX;
-    const int iy = r % bg.BY;
-    const int iz = (b & 1) ? bg.BZ - 1 - izs : izs;
-    int bz, bx, by;
-    block_coords(b, bg, bz, bx, by);
-    const int cz = bz * bg.BZ + iz, cx = bx * bg.BX + ix, cy = by * bg.BY + iy;
-    if (cz >= g.M3 || cx >= g.M1 || cy >= g.M2) return -1;
-    return ((long long)cz * g.M1 + cx) * g.M2 + cy;
+// Zeroes the cell counts of both orders.
+__global__ void bin_clear_kernel(BinBufs b) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n1 = b.ncl + 1, n2 = b.ncb + 1;
+    if (k < n1) b.cnt_lex[k] = 0;
+    else if (k < n1 + n2) b.cnt_blk[k - n1] = 0;
 }
 
-// Counts of the block-order cells from the lex cell starts (entry
-// ncell_blk, the scan's total, is zero).
-__global__ void bin_blk_counts_kernel(long long ncell_blk, Geo g, BinGeo bg,
-                                      const int* __restrict__ lex_start,
-                                      int* __restrict__ cnt_blk) {
-    const long long kb = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (kb > ncell_blk) return;
-    int n = 0;
-    if (kb < ncell_blk) {
-        const long long c = lex_of_blk(kb, g, bg);
-        if (c >= 0) n = lex_start[c + 1] - lex_start[c];
+__device__ __forceinline__ int wave_sum_int(int v) {
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+__device__ __forceinline__ int wave_incl_scan_int(int v) {
+    const int lane = threadIdx.x & 63;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
     }
-    cnt_blk[kb] = n;
+    return v;
 }
 
-// Each block-order cell takes the entries of its lex cell in the same
-// order (input index order, after bin_sort_cells_kernel).
-__global__ void bin_blk_perm_kernel(long long ncell_blk, Geo g, BinGeo bg,
-                                    const int* __restrict__ lex_start,
-                                    const int* __restrict__ lex_perm,
-                                    const int* __restrict__ blk_start,
-                                    int* __restrict__ blk_perm) {
-    const long long kb = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (kb >= ncell_blk) return;
-    const int o = blk_start[kb], n = blk_start[kb + 1] - o;
-    if (n == 0) return;
-    const int s = lex_start[lex_of_blk(kb, g, bg)];
-    for (int k = 0; k < n; ++k) blk_perm[o + k] = lex_perm[s + k];
-}
+// Exclusive scan of n counts into starts (start[k] = sum of cnt[0..k)).
+struct ScanJob {
+    const int* cnt;
+    int* start;
+    long long n;
+    const int* tsum;   // particles per tile of kScanTile counts
+    int ntiles;
+};
 
-__global__ void bin_scatter_kernel(long long N, const int* __restrict__ key,
-                                   const int* __restrict__ slot,
-                                   const int* __restrict__ start,
-                                   int* __restrict__ perm) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    perm[start[key[i]] + slot[i]] = (int)i;
-}
-
-// Sort each cell's entries by input index so the particle order (and the
-// floating-point summation order downstream) does not depend on the order
-// the atomics were served in.
-__global__ void bin_sort_cells_kernel(long long ncell,
-                                      const int* __restrict__ start,
-                                      int* __restrict__ perm) {
-    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    const int s = start[c], e = start[c + 1];
-    for (int i = s + 1; i < e; ++i) {
-        int v = perm[i];
-        int j = i - 1;
-        while (j >= s && perm[j] > v) {
-            perm[j + 1] = perm[j];
-            --j;
+// Loads the kScanItems counts of thread tid of tile t (zeros past n).
+__device__ __forceinline__ bool scan_load(const ScanJob& j, int t, int tid,
+                                          int (&v)[kScanItems]) {
+    const long long base = (long long)t * kScanTile + (long long)tid * kScanItems;
+    const bool full = base + kScanItems <= j.n;
+    if (full) {
+        const int4* p = reinterpret_cast<const int4*>(j.cnt + base);
+#pragma unroll
+        for (int k = 0; k < kScanItems / 4; ++k) {
+            const int4 c = p[k];
+            v[4 * k] = c.x; v[4 * k + 1] = c.y; v[4 * k + 2] = c.z; v[4 * k + 3] = c.w;
         }
-        perm[j + 1] = v;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = base + k < j.n ? j.cnt[base + k] : 0;
     }
+    return full;
+}
+
+// Particles per scan tile of both orders (one workgroup per tile), the
+// first pass of the reduce-then-scan.
+__global__ __launch_bounds__(256) void bin_tile_sum_kernel(ScanJob a, ScanJob b,
+                                                           int* __restrict__ tsum) {
+    __shared__ int red[4];
+    int t = blockIdx.x;
+    const bool second = t >= a.ntiles;
+    const ScanJob j = second ? b : a;
+    if (second) t -= a.ntiles;
+    int v[kScanItems];
+    scan_load(j, t, threadIdx.x, v);
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) tot += v[k];
+    tot = wave_sum_int(tot);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) tsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Both orders' scans in one launch, the second pass of the reduce-then-scan:
+// workgroups [0, a.ntiles) scan job a, the rest job b.  A workgroup adds the
+// tile sums before its own tile for its offset (a few thousand integers
+// from L2 at most), then scans its kScanTile counts: kScanItems consecutive
+// counts per thread, a wave scan of the thread totals and the four wave
+// totals through LDS.
+__global__ __launch_bounds__(256) void bin_scan_kernel(ScanJob a, ScanJob b) {
+    __shared__ int red[4];
+    int t = blockIdx.x;
+    const bool second = t >= a.ntiles;
+    const ScanJob j = second ? b : a;
+    if (second) t -= a.ntiles;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+
+    int pre = 0;
+    for (int k = tid; k < t; k += 256) pre += j.tsum[k];
+    pre = wave_sum_int(pre);
+    if (lane == 0) red[w] = pre;
+    __syncthreads();
+    pre = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+
+    const long long base = (long long)t * kScanTile + (long long)tid * kScanItems;
+    int v[kScanItems];
+    const bool full = scan_load(j, t, tid, v);
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int c = v[k];
+        v[k] = tot;
+        tot += c;
+    }
+    const int incl = wave_incl_scan_int(tot);
+    if (lane == 63) red[w] = incl;
+    __syncthreads();
+    int off = pre + incl - tot;
+    for (int k = 0; k < w; ++k) off += red[k];
+    if (full) {
+        int4* p = reinterpret_cast<int4*>(j.start + base);
+#pragma unroll
+        for (int k = 0; k < kScanItems / 4; ++k)
+            p[k] = make_int4(off + v[4 * k], off + v[4 * k + 1], off + v[4 * k + 2],
+                             off + v[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < j.n) j.start[base + k] = off + v[k];
+    }
+}
+
+// Lex order by arrival: particle i at its cell start plus its slot.
+__global__ void bin_scatter_kernel(long long N, BinBufs b,
+                                   const int* __restrict__ start) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    b.tmp[start[b.key_lex[i]] + b.slot[i]] = (int)i;
+}
+
+// Final positions: inside its cell a particle takes the rank of its input
+// index among the cell's particles, so both orders (and every floating-point
+// sum downstream) are independent of the order in which the atomics were
+// served.  A cell of the block order holds the same particles as its lex
+// cell, so the rank is the same in both.
+__global__ void bin_rank_kernel(long long N, BinBufs b,
+                                const int* __restrict__ lex_start,
+                                const int* __restrict__ blk_start,
+                                int* __restrict__ lex_perm,
+                                int* __restrict__ blk_perm) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int kl = b.key_lex[i];
+    const int s = lex_start[kl], e = lex_start[kl + 1];
+    int r = 0;
+    for (int k = s; k < e; ++k) r += b.tmp[k] < (int)i;
+    lex_perm[s + r] = (int)i;
+    blk_perm[blk_start[b.key_blk[i]] + r] = (int)i;
 }
 
 template <typename T>
@@ -373,13 +446,15 @@ __device__ __forceinline__ void bin_gather_one(const T* __restrict__ xin,
     o.cz[p] = cz;
 }
 
+// Sorted copies of the particles in both orders.
 template <typename T>
 __global__ void bin_gather_kernel(const T* __restrict__ xin,
                                   const T* __restrict__ qin, long long N,
-                                  Geo g, DevParticles<T> o) {
+                                  Geo g, DevParticles<T> lex, DevParticles<T> blk) {
     long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    bin_gather_one<T>(xin, qin, p, g, o);
+    bin_gather_one<T>(xin, qin, p, g, lex);
+    bin_gather_one<T>(xin, qin, p, g, blk);
 }
 
 // ------------------------------------------------------------------------
@@ -1618,23 +1693,13 @@ template <typename T>
 __global__ void bbin_keys_kernel(const T* __restrict__ xin, long long N,
                                  const int* __restrict__ sys_of,
                                  const SysDesc<T>* __restrict__ sys,
-                                 int* __restrict__ key_lex,
-                                 int* __restrict__ key_blk,
-                                 int* __restrict__ slot_lex,
-                                 int* __restrict__ slot_blk,
-                                 int* __restrict__ cnt_lex,
-                                 int* __restrict__ cnt_blk) {
+                                 BinBufs b) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const SysDesc<T>& sd = sys[sys_of[i]];
     int kl, kb;
     cell_keys<T>(xin, i, sd.g, sd.bg, kl, kb);
-    kl += (int)sd.cl0;
-    kb += (int)sd.cb0;
-    key_lex[i] = kl;
-    key_blk[i] = kb;
-    slot_lex[i] = atomicAdd(&cnt_lex[kl], 1);
-    slot_blk[i] = atomicAdd(&cnt_blk[kb], 1);
+    count_keys(i, kl + (int)sd.cl0, kb + (int)sd.cb0, b);
 }
 
 // Sorted position p belongs to the same system as its input index.
@@ -1643,10 +1708,12 @@ __global__ void bbin_gather_kernel(const T* __restrict__ xin,
                                    const T* __restrict__ qin, long long N,
                                    const int* __restrict__ sys_of,
                                    const SysDesc<T>* __restrict__ sys,
-                                   DevParticles<T> o) {
+                                   DevParticles<T> lex, DevParticles<T> blk) {
     long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    bin_gather_one<T>(xin, qin, p, sys[sys_of[p]].g, o);
+    const Geo& g = sys[sys_of[p]].g;
+    bin_gather_one<T>(xin, qin, p, g, lex);
+    bin_gather_one<T>(xin, qin, p, g, blk);
 }
 
 template <typename T, int P>
@@ -1836,40 +1903,44 @@ int launch_fill_int(int* p, long long n, int v, hipStream_t s) {
     return 0;
 }
 
+// Clears the counts, then (after the key kernel has counted) scans both
+// orders, places the particles by arrival and then by rank.
+static int bin_clear(const BinBufs& b, hipStream_t s) {
+    const long long n = b.ncl + 1 + b.ncb + 1;
+    hipLaunchKernelGGL(bin_clear_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, b);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
+static int bin_sort(long long N, const BinBufs& b, int* lex_start, int* blk_start,
+                    int* lex_perm, int* blk_perm, hipStream_t s) {
+    const ScanJob ja{b.cnt_lex, lex_start, b.ncl + 1, b.tsum, b.ntl};
+    const ScanJob jb{b.cnt_blk, blk_start, b.ncb + 1, b.tsum + b.ntl, b.ntb};
+    hipLaunchKernelGGL(bin_tile_sum_kernel, dim3(b.ntl + b.ntb), dim3(256), 0, s, ja, jb,
+                       b.tsum);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(b.ntl + b.ntb), dim3(256), 0, s, ja, jb);
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(N, 256)), dim3(256), 0, s, N, b,
+                       (const int*)lex_start);
+    hipLaunchKernelGGL(bin_rank_kernel, dim3(nblk(N, 256)), dim3(256), 0, s, N, b,
+                       (const int*)lex_start, (const int*)blk_start, lex_perm, blk_perm);
+    SE1P_CHECK_LAUNCH();
+    return 0;
+}
+
 template <typename T>
 int launch_bin(const T* x_in, const T* q_in, long long N, const Geo& g,
-               const BinGeo& bg, int* key_lex, int* slot_lex, int* cnt_lex,
-               int* cnt_blk, DevParticles<T>& lex, DevParticles<T>& blk,
-               void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s) {
-    // counting sort into the lex order; the block order is then a
-    // permutation of whole lex cells
+               const BinGeo& bg, const BinBufs& b, DevParticles<T>& lex,
+               DevParticles<T>& blk, hipStream_t s) {
+    // counting sort into the lex and block orders (the block order numbers
+    // the same cells, so both share each particle's rank in its cell)
     int rc;
-    if ((rc = launch_fill_int(cnt_lex, bg.ncell_lex + 1, 0, s))) return rc;
+    if ((rc = bin_clear(b, s))) return rc;
     hipLaunchKernelGGL(bin_keys_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0, s,
-                       x_in, N, g, key_lex, slot_lex, cnt_lex);
+                       x_in, N, g, bg, b);
     SE1P_CHECK_LAUNCH();
-    size_t tb = scan_tmp_bytes;
-    if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb, cnt_lex, lex.start,
-                                         (int)(bg.ncell_lex + 1), s) != hipSuccess)
-        return -5;
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(N, 256)), dim3(256), 0, s,
-                       N, key_lex, slot_lex, lex.start, lex.perm);
-    hipLaunchKernelGGL(bin_sort_cells_kernel, dim3(nblk(bg.ncell_lex, 256)),
-                       dim3(256), 0, s, bg.ncell_lex, lex.start, lex.perm);
-    hipLaunchKernelGGL(bin_blk_counts_kernel, dim3(nblk(bg.ncell_blk + 1, 256)),
-                       dim3(256), 0, s, bg.ncell_blk, g, bg, lex.start, cnt_blk);
-    SE1P_CHECK_LAUNCH();
-    tb = scan_tmp_bytes;
-    if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb, cnt_blk, blk.start,
-                                         (int)(bg.ncell_blk + 1), s) != hipSuccess)
-        return -5;
-    hipLaunchKernelGGL(bin_blk_perm_kernel, dim3(nblk(bg.ncell_blk, 256)), dim3(256),
-                       0, s, bg.ncell_blk, g, bg, lex.start, lex.perm, blk.start,
-                       blk.perm);
+    if ((rc = bin_sort(N, b, lex.start, blk.start, lex.perm, blk.perm, s))) return rc;
     hipLaunchKernelGGL(bin_gather_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0,
-                       s, x_in, q_in, N, g, lex);
-    hipLaunchKernelGGL(bin_gather_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0,
-                       s, x_in, q_in, N, g, blk);
+                       s, x_in, q_in, N, g, lex, blk);
     SE1P_CHECK_LAUNCH();
     return 0;
 }
@@ -2163,33 +2234,15 @@ static int batch_p(const BatchArgs<T>& a, const T* x, const T* q, T* phi,
     int rc;
     // counts and queue counters are cleared by kernels (no memset nodes if
     // the sequence is captured in a graph)
-    if ((rc = launch_fill_int(a.cnt_lex, a.ncl + 1, 0, s))) return rc;
-    if ((rc = launch_fill_int(a.cnt_blk, a.ncb + 1, 0, s))) return rc;
+    if ((rc = bin_clear(a.bins, s))) return rc;
     if ((rc = launch_fill_int(a.qctr, kNumQueues, 0, s))) return rc;
     hipLaunchKernelGGL(bbin_keys_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0, s,
-                       x, N, a.sys_of, a.sys, a.key_lex, a.key_blk, a.slot_lex,
-                       a.slot_blk, a.cnt_lex, a.cnt_blk);
+                       x, N, a.sys_of, a.sys, a.bins);
     SE1P_CHECK_LAUNCH();
-    size_t tb = a.scan_bytes;
-    if (hipcub::DeviceScan::ExclusiveSum(a.scan_tmp, tb, a.cnt_lex, a.lex.start,
-                                         (int)(a.ncl + 1), s) != hipSuccess)
-        return -5;
-    tb = a.scan_bytes;
-    if (hipcub::DeviceScan::ExclusiveSum(a.scan_tmp, tb, a.cnt_blk, a.blk.start,
-                                         (int)(a.ncb + 1), s) != hipSuccess)
-        return -5;
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(N, 256)), dim3(256), 0, s,
-                       N, a.key_lex, a.slot_lex, a.lex.start, a.lex.perm);
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk(N, 256)), dim3(256), 0, s,
-                       N, a.key_blk, a.slot_blk, a.blk.start, a.blk.perm);
-    hipLaunchKernelGGL(bin_sort_cells_kernel, dim3(nblk(a.ncl, 256)), dim3(256),
-                       0, s, a.ncl, a.lex.start, a.lex.perm);
-    hipLaunchKernelGGL(bin_sort_cells_kernel, dim3(nblk(a.ncb, 256)), dim3(256),
-                       0, s, a.ncb, a.blk.start, a.blk.perm);
+    if ((rc = bin_sort(N, a.bins, a.lex.start, a.blk.start, a.lex.perm, a.blk.perm, s)))
+        return rc;
     hipLaunchKernelGGL(bbin_gather_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0,
-                       s, x, q, N, a.sys_of, a.sys, a.lex);
-    hipLaunchKernelGGL(bbin_gather_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0,
-                       s, x, q, N, a.sys_of, a.sys, a.blk);
+                       s, x, q, N, a.sys_of, a.sys, a.lex, a.blk);
     SE1P_CHECK_LAUNCH();
     const BatchLaunch* L = a.q;
     if (flags & 1u) {
@@ -2289,9 +2342,8 @@ int batch_occupancy(int queue, int P, size_t lds, int* blocks_per_cu) {
 // explicit instantiations
 #define SE1P_INST(T)                                                           \
     template int launch_bin<T>(const T*, const T*, long long, const Geo&,       \
-                               const BinGeo&, int*, int*, int*, int*,           \
-                               DevParticles<T>&, DevParticles<T>&, void*,       \
-                               size_t, hipStream_t);                            \
+                               const BinGeo&, const BinBufs&,                   \
+                               DevParticles<T>&, DevParticles<T>&, hipStream_t); \
     template int launch_spread<T>(const DevParticles<T>&, long long,           \
                                   const Geo&, int, int, T*, T*, T*, T*,         \
                                   long long, hipStream_t);                      \
@@ -2331,15 +2383,5 @@ int batch_occupancy(int queue, int P, size_t lds, int* blocks_per_cu) {
 
 SE1P_INST(double)
 SE1P_INST(float)
-
-// Temporary storage the scan needs for n ints (0 if the query fails; the
-// scan itself then reports the error).
-size_t scan_temp_bytes(long long n) {
-    size_t tb = 0;
-    if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, (int*)nullptr, (int*)nullptr,
-                                         (int)n, (hipStream_t)0) != hipSuccess)
-        return 0;
-    return tb;
-}
 
 }  // namespace se1p

@@ -15,6 +15,29 @@ using se1p::FftDesc;
 using se1p::Geo;
 using se1p::SlabDesc;
 
+// Per-call device scratch of a plan: every buffer an evaluation writes
+// besides its outputs.  se1p_eval uses the plan's own scratch, allocated
+// with the plan for n_max particles; se1p_eval_noalloc lays the same
+// buffers out in the library's static scratch array for the call's N.
+struct PlanScratch {
+    se1p::BinBufs bins{};
+    int *lex_i[5] = {}, *blk_i[5] = {};   // cx, cy, cz, perm, start
+    void *lex_f[7] = {}, *blk_f[7] = {};  // x, y, z, q, tx, ty, tz
+    void *wz = nullptr, *wxp = nullptr, *wyq = nullptr;
+    void* Hpart = nullptr;
+    void *Hper = nullptr, *Htp = nullptr;   // SE3P: folded grid, transform output
+    void *Gk = nullptr, *Htk = nullptr;     // ik-differentiation: slab copies, field grids
+    void* Fz = nullptr;
+    void* G = nullptr;
+    void* Ht = nullptr;
+    void *phiF = nullptr, *EF = nullptr, *phiR = nullptr, *ER = nullptr;
+    double* partials = nullptr;
+    int nblk_comb = 0;
+    int* flag = nullptr;
+    double* qsum = nullptr;
+    int rs_parts = 1;       // real-space parts per 16-target chunk
+};
+
 // Geometry, tables and (for single-system plans) the device workspace.
 struct se1p_plan {
     se1p_params prm;
@@ -35,7 +58,6 @@ struct se1p_plan {
     int n0[2] = {0, 0}, nl[2] = {0, 0};
     int nslab = 0;
     int CZ = 0, KP = 0;
-    int rs_parts = 1;       // real-space parts per 16-target chunk
     bool in_batch = false;  // planned as a member of a batch: the batch, not
                             // the system alone, fills the chip
     std::vector<SlabDesc> slabs;
@@ -44,31 +66,15 @@ struct se1p_plan {
     long long slab_elems = 0;
     std::map<int, int> twoff;   // FFT length -> twiddle offset (complex elements)
 
-    // device memory (single allocation, carved)
+    // device memory: one allocation, carved into the tables below and the
+    // plan's own scratch (laid out for n_max particles)
     void* base = nullptr;
     size_t ws_bytes = 0;
-    int *key_lex = nullptr, *slot_lex = nullptr;
-    int *cnt_lex = nullptr, *cnt_blk = nullptr;
-    int *lex_i[5] = {}, *blk_i[5] = {};   // cx, cy, cz, perm, start
-    void *lex_f[7] = {}, *blk_f[7] = {};  // x, y, z, q, tx, ty, tz
-    void* scan_tmp = nullptr;
-    size_t scan_bytes = 0;
-    void *wz = nullptr, *wxp = nullptr, *wyq = nullptr;
-    void* Hpart = nullptr;
-    long long pstride = 0;
-    void *Hper = nullptr, *Htp = nullptr;   // SE3P: folded grid, transform output
-    void *Gk = nullptr, *Htk = nullptr;     // ik-differentiation: slab copies, field grids
-    void* Fz = nullptr;
-    void* G = nullptr;
-    void* Ht = nullptr;
-    void* S0 = nullptr;
-    void* tw = nullptr;
+    long long pstride = 0;      // elements between the KP partial grids
+    void* S0 = nullptr;         // FP64 k3 = 0 scaling table (in T)
+    void* tw = nullptr;         // FFT twiddles
     SlabDesc* d_slabs = nullptr;
-    void *phiF = nullptr, *EF = nullptr, *phiR = nullptr, *ER = nullptr;
-    double* partials = nullptr;
-    int nblk_comb = 0;
-    int* flag = nullptr;
-    double* qsum = nullptr;
+    PlanScratch w{};
 
     // stage timing: events[call][boundary], boundaries 0..SE1P_NSTAGE
     int timing = 0;
@@ -79,7 +85,6 @@ struct se1p_plan {
 };
 
 namespace se1p {
-size_t scan_temp_bytes(long long n);
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
@@ -88,6 +93,21 @@ int plan_check_params(const se1p_params& p);
 // Grid geometry, padded FFT sizes, slab descriptors, tiling and twiddle
 // offsets of one system (no device memory).
 int plan_geometry(se1p_plan& pl, const se1p_params& p, long long n_max);
+// Lays out the per-call scratch of an evaluation of n particles at base
+// (the plan's own workspace, or another buffer) and returns its size in
+// bytes; base = 0 only sizes it.  The ik-differentiation buffers are laid
+// out only when ik is set.
+size_t layout_scratch(const se1p_plan& pl, long long n, PlanScratch& w, uintptr_t base,
+                      bool ik = true);
+// Makes the plan's device current.
+int set_device(const se1p_plan* pl);
+// Host-side argument checks shared by the evaluation entry points.
+int eval_args(const se1p_plan* pl, long long N, const void* x, const void* q,
+              unsigned flags);
+// The evaluation proper (input checks, then the pipeline) on the plan's
+// current scratch.
+int eval_body(se1p_plan* pl, long long N, const void* x, const void* q,
+              void* phi, void* efield, double* energy, unsigned flags);
 // Host tables of a planned system: twiddles exp(-2 pi i k/n) for every length
 // in pl.twoff (interleaved re/im, laid out by pl.twoff) and the FP64
 // scaling table of slab n3 = 0, n0[0] x n0[1].

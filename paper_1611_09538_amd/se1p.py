@@ -87,6 +87,7 @@ class PlanInfo(ctypes.Structure):
         ("gather_chunks", ctypes.c_int),
         ("spread_cz", ctypes.c_int),
         ("spread_kp", ctypes.c_int),
+        ("bin_cells", ctypes.c_longlong * 2),
     ]
 
     def as_dict(self):
@@ -97,7 +98,7 @@ class PlanInfo(ctypes.Structure):
                 "n_max": self.n_max, "workspace_bytes": self.workspace_bytes,
                 "gather_block": tuple(self.gather_block),
                 "gather_chunks": self.gather_chunks, "spread_cz": self.spread_cz,
-                "spread_kp": self.spread_kp}
+                "spread_kp": self.spread_kp, "bin_cells": tuple(self.bin_cells)}
 
 
 class CostModel(ctypes.Structure):
@@ -132,7 +133,7 @@ QUEUES = ["spread", "zfft", "rowfwd", "cols", "rowinv", "zifft", "gather",
 # every symbol include/se1p.h declares
 EXPORTS = [
     "se1p_suggest_params", "se1p_plan_create", "se1p_plan_destroy",
-    "se1p_plan_get_info", "se1p_set_stream", "se1p_eval", "se1p_spread",
+    "se1p_plan_get_info", "se1p_set_stream", "se1p_eval", "se1p_bin", "se1p_spread",
     "se1p_kspace_solve", "se1p_gather", "se1p_error_string", "se1p_version",
     "se1p_timing_enable", "se1p_timing_select", "se1p_timing_read", "se1p_calibrate",
     "se1p_autotune", "se1p_batch_create", "se1p_batch_destroy",
@@ -175,6 +176,8 @@ def _lib():
     lib.se1p_set_stream.argtypes = [vp, vp]
     lib.se1p_eval.restype = i
     lib.se1p_eval.argtypes = [vp, ll, vp, vp, vp, vp, vp, u]
+    lib.se1p_bin.restype = i
+    lib.se1p_bin.argtypes = [vp, ll, vp, vp, vp, vp, vp, vp]
     lib.se1p_spread.restype = i
     lib.se1p_spread.argtypes = [vp, ll, vp, vp, vp]
     lib.se1p_kspace_solve.restype = i
@@ -348,6 +351,21 @@ class Plan:
     def grid_shape(self):
         i = self.info
         return (i["M3"], i["Mt"][0], i["Mt"][1])
+
+    def bin(self, x, q):
+        """Binning stage: (lex_perm, lex_start, blk_perm, blk_start) as
+        int32 device tensors (se1p_bin)."""
+        torch = _torch()
+        self._sync_stream()
+        x, q = self._prep(x, q)
+        N = x.shape[0]
+        nl, nb = self.info["bin_cells"]
+        kw = dict(dtype=torch.int32, device=x.device)
+        out = (torch.empty(N, **kw), torch.empty(nl + 1, **kw),
+               torch.empty(N, **kw), torch.empty(nb + 1, **kw))
+        _check(_lib().se1p_bin(self._h, N, _ptr(x), _ptr(q), *[_ptr(t) for t in out]),
+               "se1p_bin")
+        return out
 
     def spread(self, x, q):
         torch = _torch()

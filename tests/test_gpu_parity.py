@@ -284,6 +284,33 @@ def test_input_errors():
     assert e.value.code == se1p.ERR_TOO_MANY
 
 
+def test_check_input_accepts_fp32_rounded_neutral_charges():
+    """FP32 plans: charges neutral in FP64 and rounded to FP32 (|sum q| up to
+    about sqrt(N) 3e-8) pass SE1P_CHECK_INPUT; a charge excess of 1e-3 sum |q|
+    is still rejected."""
+    dev = _dev()
+    se1p = _se1p()
+    n = 2000
+    plan, c = _plan("small", n, precision="fp32")
+    rng = np.random.default_rng(21)
+    x = workloads.uniform_positions(rng, n, c["box"])
+    q = workloads.neutral_uniform(rng, n)
+    xt = torch.tensor(x, device=dev, dtype=torch.float32)
+    q32 = torch.tensor(q, device=dev, dtype=torch.float32)
+    qs = float(q32.double().sum().abs() / q32.double().abs().sum())
+    _say(f"FP32 neutral check: |sum q| / sum |q| = {qs:.2e}")
+    assert qs > 1e-10          # the FP64 bar would reject these charges
+    phi, _, _ = plan.eval(xt, q32, flags=se1p.ALL | se1p.CHECK_INPUT)
+    torch.cuda.synchronize()
+    assert torch.isfinite(phi).all()
+    qb = q32.clone()
+    qb[0] += 1e-3 * float(q32.abs().sum())
+    with pytest.raises(se1p.SE1PError) as e:
+        plan.eval(xt, qb, flags=se1p.ALL | se1p.CHECK_INPUT)
+    assert e.value.code == se1p.ERR_NONNEUTRAL
+    plan.close()
+
+
 def test_adaptive_transform_matches_plain_upsampled():
     """Upsampling only the slabs 0 < |k3| <= 2 pi n_l / L3 (eq. upsamplings)
     must reproduce the plain upsampled transform (every slab upsampled) to
