@@ -61,6 +61,8 @@ extern "C" {
 #define SE1P_ERR_NOMEM       -6  /* device allocation failed */
 #define SE1P_ERR_TOO_MANY    -7  /* N larger than the plan's n_max */
 #define SE1P_ERR_UNSUPPORTED -8  /* valid request outside what this library supports */
+#define SE1P_ERR_SCRATCH     -9  /* the call needs more scratch than the static
+                                    buffer of se1p_eval_noalloc holds */
 
 /* ---- precision ---------------------------------------------------------- */
 #define SE1P_FP64 0
@@ -229,6 +231,32 @@ int se1p_set_stream(se1p_plan* plan, void* stream);
  */
 int se1p_eval(se1p_plan* plan, long long N, const void* x, const void* q,
               void* phi, void* efield, double* energy, unsigned flags);
+
+/*
+ * se1p_eval_noalloc -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the evaluation of se1p_eval, same arguments, flags and
+ * results, with every per-call scratch buffer (binning arrays, weights,
+ * partial grids, spectra, per-particle partial results, energy partials)
+ * placed in one static device array of SE1P_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends, instead of
+ * the plan's own scratch.  It allocates nothing and leaves the plan's own
+ * scratch untouched; the plan supplies geometry and tables only, so N is
+ * not limited by the plan's n_max (which sized the plan's scratch and
+ * tuned its tiles) but by the static array: SE1P_ERR_SCRATCH when the
+ * call's scratch (a function of the grid and N; the ik buffers count only
+ * with SE1P_FIELD_IK) exceeds it, checked on the host before anything is
+ * enqueued.  The N = 1e5 FP64 system with P = 24 and a 64 x 96 x 96 grid
+ * needs about 190 MB.
+ * All calls on one GPU share its array and leave their contents in it;
+ * every buffer a call reads is written or cleared earlier in the same call.
+ * Calls that overlap on one GPU (other host threads, other streams) race
+ * on the array and must be serialised by the caller.  The array's address
+ * on a device is looked up on the first call on that device.
+ */
+#define SE1P_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int se1p_eval_noalloc(se1p_plan* plan, long long N, const void* x, const void* q,
+                      void* phi, void* efield, double* energy, unsigned flags);
 
 /*
  * Stages of the k-space path, for testing and for callers that bring their

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libse1p.so")
 
-SOURCES = ["se1p_kernels.hip", "se1p_host.cpp", "se1p_batch.cpp"]
+SOURCES = ["se1p_kernels.hip", "se1p_host.cpp", "se1p_batch.cpp", "se1p_noalloc.cpp"]
 
 ARCH = "gfx950"
 COMMON = [

@@ -703,6 +703,8 @@ const char* se1p_error_string(int code) {
         case SE1P_ERR_NOMEM: return "device allocation failed";
         case SE1P_ERR_TOO_MANY: return "more particles than the plan allows";
         case SE1P_ERR_UNSUPPORTED: return "unsupported parameter combination";
+        case SE1P_ERR_SCRATCH:
+            return "the call needs more scratch than se1p_eval_noalloc's static buffer holds";
         default: return "unknown error";
     }
 }

@@ -26,6 +26,8 @@ ERR_HIP = -5
 ERR_NOMEM = -6
 ERR_TOO_MANY = -7
 ERR_UNSUPPORTED = -8
+ERR_SCRATCH = -9
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 FP64 = 0
 FP32 = 1
@@ -133,7 +135,8 @@ QUEUES = ["spread", "zfft", "rowfwd", "cols", "rowinv", "zifft", "gather",
 # every symbol include/se1p.h declares
 EXPORTS = [
     "se1p_suggest_params", "se1p_plan_create", "se1p_plan_destroy",
-    "se1p_plan_get_info", "se1p_set_stream", "se1p_eval", "se1p_bin", "se1p_spread",
+    "se1p_plan_get_info", "se1p_set_stream", "se1p_eval", "se1p_eval_noalloc",
+    "se1p_bin", "se1p_spread",
     "se1p_kspace_solve", "se1p_gather", "se1p_error_string", "se1p_version",
     "se1p_timing_enable", "se1p_timing_select", "se1p_timing_read", "se1p_calibrate",
     "se1p_autotune", "se1p_batch_create", "se1p_batch_destroy",
@@ -176,6 +179,8 @@ def _lib():
     lib.se1p_set_stream.argtypes = [vp, vp]
     lib.se1p_eval.restype = i
     lib.se1p_eval.argtypes = [vp, ll, vp, vp, vp, vp, vp, u]
+    lib.se1p_eval_noalloc.restype = i
+    lib.se1p_eval_noalloc.argtypes = [vp, ll, vp, vp, vp, vp, vp, u]
     lib.se1p_bin.restype = i
     lib.se1p_bin.argtypes = [vp, ll, vp, vp, vp, vp, vp, vp]
     lib.se1p_spread.restype = i
@@ -332,6 +337,13 @@ class Plan:
         self._sync_stream()
         _check(_lib().se1p_eval(self._h, x.shape[0], _ptr(x), _ptr(q), _ptr(phi),
                                 _ptr(E), _ptr(U), int(flags)), "se1p_eval")
+
+    def eval_noalloc_into(self, x, q, phi, E, U, flags=ALL):
+        """se1p_eval_noalloc into preallocated outputs: the library's static
+        device scratch instead of the plan's (no allocation anywhere)."""
+        self._sync_stream()
+        _check(_lib().se1p_eval_noalloc(self._h, x.shape[0], _ptr(x), _ptr(q), _ptr(phi),
+                                        _ptr(E), _ptr(U), int(flags)), "se1p_eval_noalloc")
 
     def timing_enable(self, on=True):
         _check(_lib().se1p_timing_enable(self._h, 1 if on else 0), "se1p_timing_enable")
