@@ -184,6 +184,24 @@ __device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int batch, int stride,
     return a;
 }
 
+// FP32 Gaussian weight exp(-alpha (u h)^2) of an offset u in units of h,
+// with alpha h^2 carried as two FP32 parts (c_hi + c_lo): a single rounded
+// constant would bias every weight of a launch the same way (by up to
+// alpha (u h)^2 2^-24 relative), which shows in the self-interaction
+// part of phi^F and from there in the energy.
+__device__ __forceinline__ float gauss_u(float u, float c_hi, float c_lo) {
+    const float u2 = u * u;
+    return __expf(fmaf(-c_hi, u2, -c_lo * u2));
+}
+struct GaussC {
+    float hi, lo;
+};
+__host__ __device__ __forceinline__ GaussC gauss_consts(const Geo& g) {
+    const double c = g.alpha * g.h * g.h;
+    const float hi = (float)c;
+    return {hi, (float)(c - (double)hi)};
+}
+
 // ------------------------------------------------------------------------
 // binning
 // ------------------------------------------------------------------------
@@ -490,8 +508,13 @@ __device__ __forceinline__ void spread_weight_elem(const DevParticles<T>& lx,
         T w = 0;
         if (u >= 0 && u < P) {
             const T t = isy ? lx.ty[p] : lx.tx[p];
-            const T d = (t - (T)(1 + u - P / 2)) * h;
-            w = dexp<T>(-a * d * d);
+            if constexpr (sizeof(T) == 4) {
+                const GaussC gc = gauss_consts(g);
+                w = gauss_u(t - (T)(1 + u - P / 2), gc.hi, gc.lo);
+            } else {
+                const T d = (t - (T)(1 + u - P / 2)) * h;
+                w = dexp<T>(-a * d * d);
+            }
             if (isy) w = lx.q[p] * w;
         }
         (isy ? wyq : wxp)[j] = w;
@@ -499,8 +522,13 @@ __device__ __forceinline__ void spread_weight_elem(const DevParticles<T>& lx,
         const long long j = i - 2 * nxy;
         const long long p = j / P;
         const int d = (int)(j - p * P);
-        const T dz = (lx.tz[p] - (T)(1 + d - P / 2)) * h;
-        wz[j] = dexp<T>(-a * dz * dz);
+        if constexpr (sizeof(T) == 4) {
+            const GaussC gc = gauss_consts(g);
+            wz[j] = gauss_u(lx.tz[p] - (T)(1 + d - P / 2), gc.hi, gc.lo);
+        } else {
+            const T dz = (lx.tz[p] - (T)(1 + d - P / 2)) * h;
+            wz[j] = dexp<T>(-a * dz * dz);
+        }
     }
 }
 
@@ -1045,6 +1073,27 @@ __device__ __forceinline__ void gather_body(
             ryB = dexp<T>(a * h * ((T)2 * dyB - h));
         }
         T phi = 0, ex = 0, ey = 0, ez = 0;
+        // FP32: every weight of the particle once, from offsets in units of
+        // h (x and y in registers, z one per plane), and the sums taken per
+        // row, then per plane, then over the planes, so that no level adds
+        // the window's small edge terms to a much larger running sum (a flat
+        // FP32 sum of the P^3 terms drops them and comes out low by a few
+        // 1e-7, the same way for every particle)
+        [[maybe_unused]] T wxa[sizeof(T) == 4 ? P : 1], txa[sizeof(T) == 4 ? P : 1];
+        [[maybe_unused]] T wya[sizeof(T) == 4 ? P : 1], tya[sizeof(T) == 4 ? P : 1];
+        [[maybe_unused]] GaussC gc{};
+        if constexpr (sizeof(T) == 4) {
+            gc = gauss_consts(g);
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const T ux = tx - (T)(1 + u - P / 2);
+                const T uy = ty - (T)(1 + u - P / 2);
+                wxa[u] = gauss_u(ux, gc.hi, gc.lo);
+                txa[u] = ux * wxa[u];
+                wya[u] = gauss_u(uy, gc.hi, gc.lo);
+                tya[u] = uy * wya[u];
+            }
+        }
 
         // Planes stream straight from global memory into LDS (16-byte
         // global_load_lds chunks, 64 per instruction), one plane ahead of
@@ -1076,12 +1125,42 @@ __device__ __forceinline__ void gather_body(
             const int uz = ozmin + ip;
             const int dzi = uz - oz;
             const bool zin = act && dzi >= 0 && dzi < P;
+            if constexpr (sizeof(T) == 4) {
+                if (zin) {
+                    const T vz = tz - (T)(dzi + 1 - P / 2);
+                    const T wzv = gauss_u(vz, gc.hi, gc.lo);
+                    const T* base = cur + ox * ldy + oy;
+                    T sp = 0, spx = 0, spy = 0;
+#pragma unroll
+                    for (int dx = 0; dx < P; ++dx) {
+                        const T* row = base + dx * ldy;
+                        T sy = 0, sty = 0;
+#pragma unroll
+                        for (int u = 0; u < P; ++u) {
+                            const T hv = row[u];
+                            sy = fma(wya[u], hv, sy);
+                            if constexpr (FIELD) sty = fma(tya[u], hv, sty);
+                        }
+                        sp = fma(wxa[dx], sy, sp);
+                        if constexpr (FIELD) {
+                            spx = fma(txa[dx], sy, spx);
+                            spy = fma(wxa[dx], sty, spy);
+                        }
+                    }
+                    phi = fma(wzv, sp, phi);
+                    if constexpr (FIELD) {
+                        ex = fma(wzv, spx, ex);
+                        ey = fma(wzv, spy, ey);
+                        ez = fma(vz * wzv, sp, ez);
+                    }
+                }
+            }
             const T dz = (tz - (T)(dzi + 1 - P / 2)) * h;
-            const T wzv = zin ? dexp<T>(-a * dz * dz) : (T)0;
+            const T wzv = (zin && sizeof(T) == 8) ? dexp<T>(-a * dz * dz) : (T)0;
             const T tzw = dz * wzv;
             // lanes are sorted by z, so at the first and last planes whole
             // groups of lanes are idle and issue no LDS reads
-            if (zin) {
+            if (sizeof(T) == 8 && zin) {
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
                     // y weights of this half of the window (registers)
@@ -1142,7 +1221,8 @@ __device__ __forceinline__ void gather_body(
             const long long o = perm[p];
             if (phi_out) phi_out[o * phi_stride] = scale * phi;
             if (FIELD && E_out) {
-                const T f = scale * (T)2 * a;
+                // FP32 sums offsets in units of h: the factor takes h
+                const T f = sizeof(T) == 4 ? scale * (T)(2.0 * g.alpha * g.h) : scale * (T)2 * a;
                 E_out[3 * o] = f * ex;
                 E_out[3 * o + 1] = f * ey;
                 E_out[3 * o + 2] = f * ez;

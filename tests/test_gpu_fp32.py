@@ -74,7 +74,7 @@ def test_fp32_small_vs_fp64():
     assert max(e) < 1e-5
 
 
-@pytest.mark.parametrize("n,bar", [(2, 1e-4), (66, 1e-5), (258, 1e-5)])
+@pytest.mark.parametrize("n,bar", [(2, 1e-5), (66, 1e-5), (258, 1e-5)])
 def test_fp32_ragged_vs_fp64(n, bar):
     # Few particles: the k-space and real-space parts can cancel in the
     # total, and FP32 rounds each part; the bar is relative to the largest
@@ -118,11 +118,12 @@ def test_fp32_1e6_vs_fp64_gpu_and_oracle():
     o64 = (_rel(p64[tg], g["phi"]), _rel(E64[tg], g["E"]))
     _say("FP32 vs oracle (%d targets): phi %.2e  E %.2e" % (len(tg), *o32))
     _say("FP64 GPU vs oracle (method error at these parameters): phi %.2e  E %.2e" % o64)
-    # U = 1/2 sum q phi of a neutral system cancels: its FP32 error is
-    # stated against the size of the summed terms, 1/2 sum |q phi|
+    # U = 1/2 sum q phi cancels: the k-space part and the self term are each
+    # some 60 times U here, so U needs phi^F to a few 1e-7 with no bias; the
+    # per-result bar of 1e-5 applies to U itself
     Uterms = 0.5 * np.sum(np.abs(q * p64))
-    eU = abs(U32 - U64) / Uterms
-    _say("U: rel %.2e, relative to 1/2 sum |q phi| %.2e" % (vs64[2], eU))
     assert abs(U32 - 0.5 * np.dot(q, p32)) <= 1e-6 * Uterms
-    assert max(vs64[:2]) < 1e-5 and eU < 1e-5
+    assert max(vs64) < 1e-5
     assert max(o32) < 1e-5
+    # the FP64 path at the same parameters: the method error it was set for
+    assert max(o64) < 1e-5

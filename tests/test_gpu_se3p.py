@@ -102,7 +102,7 @@ def test_paper_density125_system_at_1e5():
     po, Eo = oracle.ewald3p_total(x, q, box, 4.0, targets=tg)
     dphi, dE = _rel(phi[tg], po), _rel(E[tg], Eo)
     _say(f"rel-rms phi {dphi:.2e}  E {dE:.2e}")
-    assert dphi < 1e-5 and dE < 1e-4
+    assert dphi < 1e-5 and dE < 1e-5
 
 
 def test_stage_calls_rejected_for_periodic_plan():
