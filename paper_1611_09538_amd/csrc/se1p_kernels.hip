@@ -1037,6 +1037,12 @@ __device__ __forceinline__ void gather_body(
     const int lane = threadIdx.x;
     const int plane_stride = Ux * ldy;
     const int n16 = plane_stride * (int)sizeof(T) / 16;
+    // 16-byte chunk c of a staged plane starts at row c per16 / ldy, column
+    // c per16 % ldy of the footprint; lane's first chunk and the step of 64
+    // chunks, so the staging loop carries row and column without dividing
+    constexpr int per16 = 16 / (int)sizeof(T);
+    const int rr0 = lane * per16 / ldy, cc0 = lane * per16 - rr0 * ldy;
+    const int rstep = 64 * per16 / ldy, cstep = 64 * per16 - rstep * ldy;
 
     for (int c0 = s + 64 * slot; c0 < e; c0 += 64 * CH) {
         const int p = c0 + lane;
@@ -1101,17 +1107,19 @@ __device__ __forceinline__ void gather_body(
         auto stage = [&](int ip, T* buf) {
             const T* src = Ht + (long long)imod(zl0 + ozmin + ip, g.M3) * g.ncol +
                            (long long)X0u * g.Mt2 + Y0u;
-            constexpr int per16 = 16 / (int)sizeof(T);
+            int rr = rr0, cc = cc0;
             for (int k = 0; k * 64 < n16; ++k) {
-                const int c = k * 64 + lane;
-                if (c < n16) {
-                    const int dd = c * per16;
-                    const int rr = dd / ldy;
-                    const int cc = dd - rr * ldy;
+                if (k * 64 + lane < n16) {
                     __builtin_amdgcn_global_load_lds(
-                        (const void*)(src + (long long)rr * g.Mt2 + cc),
+                        (const void*)(src + (rr * g.Mt2 + cc)),
                         (__attribute__((address_space(3))) void*)(buf + k * 64 * per16),
                         16, 0, 0);
+                }
+                rr += rstep;
+                cc += cstep;
+                if (cc >= ldy) {
+                    cc -= ldy;
+                    ++rr;
                 }
             }
         };

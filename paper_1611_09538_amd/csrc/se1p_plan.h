@@ -7,7 +7,7 @@
 #include <map>
 #include <vector>
 
-#include "../../include/se1p.h"
+#include "se1p.h"
 #include "se1p_internal.h"
 
 using se1p::BinGeo;
