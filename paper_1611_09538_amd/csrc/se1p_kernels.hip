@@ -612,48 +612,78 @@ __device__ __forceinline__ void spread_body(
     int rsA, reA;
     load_rows(cz0, rsA, reA);
 
+    // Per z cell the rows' particles form one list (row k, then row k + 1,
+    // in lex order), dealt round robin to the waves.  Lane i of a wave
+    // looks up the wave's i-th particle of the list once: its index, x cell
+    // and y cell stay in registers and are read back with readlane, so the
+    // loop over the particles has no load whose address waits on another
+    // load (only the weight loads of the particle itself).
+    __shared__ int lst_incl[W][64], lst_off[W][64];
     for (int ci = 0; ci < CZ; ++ci) {
         int rsB = 0, reB = 0;
         if (ci + 1 < CZ) load_rows(cz0 + ci + 1, rsB, reB);
         {
-            for (int k = 0; k < nr; ++k) {
-                const int cx = cxlo + k;
-                const int s = __builtin_amdgcn_readlane(rsA, k);
-                const int e = __builtin_amdgcn_readlane(reA, k);
-                // support index of this lane's column for the row, and of
-                // its y point for each particle: the weight is zero outside
-                // [0, P).  Padded rows are read as they are; unpadded ones
-                // with the index clamped into the particle's row.
-                const int ux = lx - (cx + 1);
-                const bool vx = (unsigned)ux < (unsigned)P;
-                const int offx = pad > 0 ? ux + pad : min(max(ux, 0), P - 1);
-                auto coef = [&](int pp, int cyp) -> T {
+            const int len = lane < nr ? reA - rsA : 0;
+            int incl = len;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int v = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += v;
+            }
+            const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+            lst_incl[wv][lane] = incl;        // particles of rows 0..lane
+            lst_off[wv][lane] = rsA - (incl - len);   // index = off + list position
+            // the wave's own LDS rows: written and read by this wave only
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            for (int base = wv; base < total; base += 64 * W) {
+                // lane i: list position base + W i, its row by binary search
+                const int gi = base + W * lane;
+                int k = 0;                    // rows 0..k-1 end at or before gi
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1)
+                    if (k + step <= 63 && lst_incl[wv][k + step - 1] <= gi) k += step;
+                const bool valid = gi < total;
+                const int pi = valid ? lst_off[wv][k] + gi : 0;
+                const int cxi = cxlo + k;
+                const int cyi = valid ? pcy[pi] : 0;
+                const int n = min(64, (total - base + W - 1) / W);
+                auto coef = [&](int pp, int cxp, int cyp) -> T {
+                    const int ux = lx - (cxp + 1);
                     const int uy = ly - (cyp + 1);
                     if constexpr (pad > 0) {
-                        return wxp[(long long)pp * PW + offx] *
+                        return wxp[(long long)pp * PW + ux + pad] *
                                wyq[(long long)pp * PW + uy + pad];
                     } else {
+                        const T wx = wxp[(long long)pp * PW + min(max(ux, 0), P - 1)];
                         const T wy = wyq[(long long)pp * PW + min(max(uy, 0), P - 1)];
-                        const T wx = wxp[(long long)pp * PW + offx];
-                        return (vx && (unsigned)uy < (unsigned)P) ? wx * wy : (T)0;
+                        return ((unsigned)ux < (unsigned)P && (unsigned)uy < (unsigned)P)
+                                   ? wx * wy : (T)0;
                     }
                 };
-                int p = s + wv;
-                for (; p + W < e; p += 2 * W) {
-                    const int cyA = pcy[p], cyB = pcy[p + W];
-                    const T cA = coef(p, cyA);
-                    const T cB = coef(p + W, cyB);
-                    const T* __restrict__ zA = wz + (long long)p * P;
-                    const T* __restrict__ zB = wz + (long long)(p + W) * P;
+                // FP32: two particles per iteration (their loads in flight
+                // together); FP64: one, since two particles' z weights (2 P
+                // doubles in scalar registers) spill
+                int i = 0;
+                for (; sizeof(T) == 4 && i + 1 < n; i += 2) {
+                    const int pA = __builtin_amdgcn_readlane(pi, i);
+                    const int pB = __builtin_amdgcn_readlane(pi, i + 1);
+                    const T cA = coef(pA, __builtin_amdgcn_readlane(cxi, i),
+                                      __builtin_amdgcn_readlane(cyi, i));
+                    const T cB = coef(pB, __builtin_amdgcn_readlane(cxi, i + 1),
+                                      __builtin_amdgcn_readlane(cyi, i + 1));
+                    const T* __restrict__ zA = wz + (long long)pA * P;
+                    const T* __restrict__ zB = wz + (long long)pB * P;
 #pragma unroll
                     for (int d = 0; d < P; ++d) acc[d] = fma(cA, zA[d], acc[d]);
 #pragma unroll
                     for (int d = 0; d < P; ++d) acc[d] = fma(cB, zB[d], acc[d]);
                 }
-                if (p < e) {
-                    const int cyA = pcy[p];
-                    const T cA = coef(p, cyA);
-                    const T* __restrict__ zA = wz + (long long)p * P;
+                for (; i < n; ++i) {
+                    const int pA = __builtin_amdgcn_readlane(pi, i);
+                    const T cA = coef(pA, __builtin_amdgcn_readlane(cxi, i),
+                                      __builtin_amdgcn_readlane(cyi, i));
+                    const T* __restrict__ zA = wz + (long long)pA * P;
 #pragma unroll
                     for (int d = 0; d < P; ++d) acc[d] = fma(cA, zA[d], acc[d]);
                 }
