@@ -16,10 +16,11 @@ Extra fields:
                   event-timed duration, against the MI355X vector peak;
                   traffic from the committed FETCH_SIZE / WRITE_SIZE counter
                   summary when it was taken on the current kernel source
-  kernels         the gridding and gathering kernels against their LDS
-                  bounds (algorithmic LDS bytes per particle: w P^3 for the
-                  gather, 2 w P^3 for an LDS-tiled gridding) and the vector
-                  ALU peak
+  kernels         the gathering kernel against the nominal LDS bandwidth
+                  (algorithmic LDS bytes w P^3 per particle) and the vector
+                  ALU peak; the gridding stage against the vector FMA peak
+                  (it keeps its sums in registers), with its HBM traffic
+                  over its algorithmic bytes (particles in, grid out)
   fp32            the N = 1e6 FP32 system (2 x 2 x 1, P = 12, rel-RMS 1e-5):
                   FP32 path and the FP64 path at the same parameters
   adaptive_fft    the transform stage against the plain upsampled transform
@@ -55,10 +56,8 @@ if ROOT not in sys.path:
 METRIC = "SE1P potential+force particles/s at rel-RMS 1e-8 (FP64) and 1e-5 (FP32)"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X vector, dense
 HBM_PEAK_GBS = 8000.0
-# LDS: 256 CUs x 128 bytes per clock x 2.4 GHz; and the rate a conflict-free
-# 8-byte-per-lane read pattern reached in a microbenchmark on the MI355X
+# LDS: 256 CUs x 128 bytes per clock x 2.4 GHz (nominal)
 LDS_PEAK_TBS = 78.6
-LDS_MEASURED_TBS = 54.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1611_09538_amd", "csrc", "se1p_kernels.hip")
 
@@ -86,6 +85,9 @@ def parse():
                     help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--leg", choices=["batched"], default=None,
+                    help="run only this extra measurement and print its JSON "
+                         "(for profiling one workload)")
     return ap.parse_args()
 
 
@@ -97,6 +99,18 @@ def gather_flops(N, P):
 
 def spread_flops(N, P):
     return 2.0 * N * P ** 3
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def pair_count(x, box, rc):
@@ -414,6 +428,10 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if a.leg == "batched":
+        print(json.dumps({"batched": batched_extra(se1p, workloads, torch, dev,
+                                                   a.steps, a.warmup)}))
+        return
     x, q, box, c = workloads.make_case(a.case)
     N = x.shape[0]
     prec = se1p.FP64 if c["precision"] == "fp64" else se1p.FP32
@@ -469,29 +487,33 @@ def main():
     g_fl = gather_flops(N, P)
     g_ach = g_fl / (st_ms["gather"] * 1e-3) / 1e12
     w = 8 if dname == "f64" else 4
-    # LDS bounds: the gather reads w P^3 bytes of window values per particle;
-    # an LDS-tiled gridding reads and writes 2 w P^3 per particle
+    # the gather reads w P^3 bytes of window values from LDS per particle
     g_lds = float(N) * w * P ** 3
-    s_lds = 2.0 * float(N) * w * P ** 3
     g_tbs = g_lds / (st_ms["gather"] * 1e-3) / 1e12
-    s_tbs = s_lds / (st_ms["spread"] * 1e-3) / 1e12
+    # gridding keeps its sums in registers: bound by vector FMA issue, one
+    # FMA (2 flops) per particle and support point; its algorithmic HBM
+    # bytes are the particles in (x, y, z, q) and the grid out
     s_ach = spread_flops(N, P) / (st_ms["spread"] * 1e-3) / 1e12
+    grid_bytes = float(c["M3"]) * plan.info["Mt"][0] * plan.info["Mt"][1] * w
+    s_alg_bytes = 4.0 * w * N + grid_bytes
+    s_tr = [traffic_for(k, a.case) for k in ("spread_kernel", "spread_weights_kernel")]
+    s_traffic = None if None in s_tr else float(sum(s_tr))
     kern = {
         "gather_kernel": {"bound": "lds", "achieved": g_tbs, "peak": LDS_PEAK_TBS,
                           "unit": "TB/s", "frac": g_tbs / LDS_PEAK_TBS,
-                          "frac_of_measured_lds_peak": g_tbs / LDS_MEASURED_TBS,
                           "algorithmic_lds_bytes_per_launch": g_lds,
                           "alu_tflops": g_ach, "alu_frac": g_ach / peak,
                           "algorithmic_flops_per_launch": g_fl,
                           "avg_ms": st_ms["gather"],
                           "traffic": traffic_for("gather_kernel", a.case)},
-        "spread_stage": {"bound": "lds", "achieved": s_tbs, "peak": LDS_PEAK_TBS,
-                         "unit": "TB/s", "frac": s_tbs / LDS_PEAK_TBS,
-                         "frac_of_measured_lds_peak": s_tbs / LDS_MEASURED_TBS,
-                         "algorithmic_lds_bytes_per_launch": s_lds,
-                         "alu_tflops": s_ach, "alu_frac": s_ach / peak,
+        "spread_stage": {"bound": "alu", "achieved": s_ach, "peak": peak,
+                         "unit": "TFLOP/s", "frac": s_ach / peak,
                          "algorithmic_flops_per_launch": spread_flops(N, P),
-                         "avg_ms": st_ms["spread"]},
+                         "avg_ms": st_ms["spread"],
+                         "algorithmic_hbm_bytes": s_alg_bytes,
+                         "traffic": s_traffic,
+                         "traffic_over_algorithmic":
+                             None if s_traffic is None else s_traffic / s_alg_bytes},
     }
 
     out = {
@@ -567,7 +589,7 @@ def main():
         pg, Eg = phi.cpu().numpy(), E.cpu().numpy()
         out["cpu_baseline"] = {
             "value": nt / cpu_t, "unit": "particles/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"{nt} of {N} targets, direct Ewald1P sums at xi_o = 0.45/L3 "
                       f"(potential and field), {cpu_t:.1f} s"}
         out["rel_rms_sample"] = {
