@@ -205,12 +205,27 @@ int build_batch(se1p_batch& b) {
         for (long long k = 0; k < (b.cnt[s] + 255) / 256; ++k)
             it[kQComb].push_back({1.0, Item{s, (int)k, 0, 0}});
     }
+    // Each stage's list (generated in spatial order) is split into 8
+    // consecutive ranges of equal estimated cost, one per XCD, each sorted
+    // most expensive first.
+    std::vector<int> qb(9 * kNumQueues, 0);
     for (int k = 0; k < kNumQueues; ++k) {
-        std::stable_sort(it[k].begin(), it[k].end(),
-                         [](const std::pair<double, Item>& u,
-                            const std::pair<double, Item>& v) { return u.first > v.first; });
         if (it[k].size() >= (size_t)(1 << 30)) return SE1P_ERR_UNSUPPORTED;
         b.nitems[k] = (int)it[k].size();
+        double tot = 0.0;
+        for (auto& e : it[k]) tot += e.first;
+        int r = 1;
+        double acc = 0.0;
+        for (size_t i = 0; i < it[k].size() && r < 8; ++i) {
+            while (r < 8 && acc >= tot * r / 8.0) qb[9 * k + r++] = (int)i;
+            acc += it[k][i].first;
+        }
+        while (r < 8) qb[9 * k + r++] = b.nitems[k];
+        qb[9 * k + 8] = b.nitems[k];
+        for (int q = 0; q < 8; ++q)
+            std::stable_sort(it[k].begin() + qb[9 * k + q], it[k].begin() + qb[9 * k + q + 1],
+                             [](const std::pair<double, Item>& u,
+                                const std::pair<double, Item>& v) { return u.first > v.first; });
     }
     for (int k = 0; k < kNumQueues; ++k)
         if (lds[k] > 160 * 1024) return SE1P_ERR_UNSUPPORTED;
@@ -224,7 +239,8 @@ int build_batch(se1p_batch& b) {
         int bpc = 0;
         if (batch_occupancy<T>(k, P, lds[k], &bpc)) return SE1P_ERR_HIP;
         const long long cap = (long long)std::max(bpc, 1) * std::max(ncu, 1);
-        b.grid[k] = (int)std::max<long long>(1, std::min<long long>(b.nitems[k], cap));
+        // a multiple of 8 blocks: every XCD works on its own range
+        b.grid[k] = (int)std::max<long long>(8, cap - cap % 8);
     }
 
     // ---- workspace ----
@@ -266,7 +282,9 @@ int build_batch(se1p_batch& b) {
     int* sys_of = nullptr;
     add((void**)&sys_of, N * 4);
     add((void**)&a.partials, (size_t)std::max<long long>(ne, 1) * 8);
-    add((void**)&a.qctr, 256);
+    add((void**)&a.qctr, 8 * kQCtrStride * kNumQueues * sizeof(int));
+    int* dqb = nullptr;
+    add((void**)&dqb, qb.size() * sizeof(int));
     cplx<T>* tw = nullptr;
     add((void**)&tw, (size_t)std::max<long long>(twn, 1) * cs);
     SysDesc<T>* dsys = nullptr;
@@ -358,6 +376,8 @@ int build_batch(se1p_batch& b) {
         if (!v.empty())
             e = hipMemcpy(ditems[k], v.data(), v.size() * sizeof(Item), hipMemcpyHostToDevice);
     }
+    if (e == hipSuccess)
+        e = hipMemcpy(dqb, qb.data(), qb.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e != hipSuccess) return SE1P_ERR_HIP;
 
     a.sys = dsys;
@@ -370,6 +390,7 @@ int build_batch(se1p_batch& b) {
     a.tw = tw;
     for (int k = 0; k < kNumQueues; ++k) {
         a.q[k].items = ditems[k];
+        a.q[k].qb = dqb + 9 * k;
         a.q[k].nitems = b.nitems[k];
         a.q[k].grid = b.grid[k];
         a.q[k].lds = lds[k];

@@ -219,8 +219,11 @@ enum BatchQueue {
     kQReal, kQComb, kQEnergy, kNumQueues
 };
 
+constexpr int kQCtrStride = 32;   // ints between the queue counters (128 bytes)
+
 struct BatchLaunch {           // one queue stage
     const Item* items;          // device
+    const int* qb;              // device: bounds of the 8 per-XCD item ranges
     int nitems;
     int grid;                   // persistent blocks
     size_t lds;                 // dynamic LDS bytes
@@ -240,7 +243,7 @@ struct BatchArgs {
     const cplx<T>* tw;
     T* phiF; T* EF; T* phiR; T* ER;
     double* partials;
-    int* qctr;                  // kNumQueues counters
+    int* qctr;                  // 8 counters per queue, kQCtrStride apart
     BatchLaunch q[kNumQueues];
 };
 

@@ -1798,11 +1798,22 @@ __global__ __launch_bounds__(256) void check_kernel(
 // up; grid-shaped stages are persistent: a fixed set of blocks pulls
 // (system, tile) items from a global counter until the queue is empty, so
 // uneven systems balance across the chip without one launch per system.
-// Items are ordered by decreasing estimated cost.
-__device__ __forceinline__ int next_item(int* __restrict__ ctr) {
+// A stage's items are split into 8 ranges, one per XCD, each holding a
+// spatially contiguous part of the list (neighbouring tiles, which read the
+// same particles and grid rows, then share one L2) with about an eighth of
+// the estimated cost, most expensive items first inside the range.  The
+// dispatcher deals blocks round-robin to the XCDs, so block b pulls from
+// range b % 8, through that range's own counter (kQCtrStride ints apart, a
+// cache line each).  qb holds the 9 bounds of the stage's ranges.
+__device__ __forceinline__ int next_item(int* __restrict__ ctr,
+                                         const int* __restrict__ qb) {
     __shared__ int s_item;
     __syncthreads();                 // the previous item is done with LDS
-    if (threadIdx.x == 0) s_item = atomicAdd(ctr, 1);
+    if (threadIdx.x == 0) {
+        const int r = (int)(blockIdx.x & 7u);
+        const int i = qb[r] + atomicAdd(&ctr[r * kQCtrStride], 1);
+        s_item = i < qb[r + 1] ? i : -1;
+    }
     __syncthreads();
     return __builtin_amdgcn_readfirstlane(s_item);
 }
@@ -1851,12 +1862,12 @@ __global__ void bspread_weights_kernel(DevParticles<T> lx, long long N,
 template <typename T, int P>
 __global__ __launch_bounds__(64 * spread_waves(P)) void bspread_kernel(
     const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
-    int nitems, int* __restrict__ ctr, const T* __restrict__ wz,
+    const int* __restrict__ qb, int* __restrict__ ctr, const T* __restrict__ wz,
     const T* __restrict__ wxp, const T* __restrict__ wyq,
     const int* __restrict__ pcy, const int* __restrict__ cstart) {
     for (;;) {
-        const int it = next_item(ctr);
-        if (it >= nitems) return;
+        const int it = next_item(ctr, qb);
+        if (it < 0) return;
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
@@ -1868,10 +1879,10 @@ __global__ __launch_bounds__(64 * spread_waves(P)) void bspread_kernel(
 template <typename T>
 __global__ __launch_bounds__(256) void bzfft_kernel(
     const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
-    int nitems, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
+    const int* __restrict__ qb, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
     for (;;) {
-        const int it = next_item(ctr);
-        if (it >= nitems) return;
+        const int it = next_item(ctr, qb);
+        if (it < 0) return;
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
@@ -1882,10 +1893,10 @@ __global__ __launch_bounds__(256) void bzfft_kernel(
 template <typename T>
 __global__ __launch_bounds__(256) void browfwd_kernel(
     const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
-    int nitems, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
+    const int* __restrict__ qb, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
     for (;;) {
-        const int it = next_item(ctr);
-        if (it >= nitems) return;
+        const int it = next_item(ctr, qb);
+        if (it < 0) return;
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
@@ -1896,10 +1907,10 @@ __global__ __launch_bounds__(256) void browfwd_kernel(
 template <typename T>
 __global__ __launch_bounds__(256) void bcols_kernel(
     const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
-    int nitems, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
+    const int* __restrict__ qb, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
     for (;;) {
-        const int it = next_item(ctr);
-        if (it >= nitems) return;
+        const int it = next_item(ctr, qb);
+        if (it < 0) return;
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
@@ -1910,10 +1921,10 @@ __global__ __launch_bounds__(256) void bcols_kernel(
 template <typename T>
 __global__ __launch_bounds__(256) void browinv_kernel(
     const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
-    int nitems, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
+    const int* __restrict__ qb, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
     for (;;) {
-        const int it = next_item(ctr);
-        if (it >= nitems) return;
+        const int it = next_item(ctr, qb);
+        if (it < 0) return;
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
@@ -1924,10 +1935,10 @@ __global__ __launch_bounds__(256) void browinv_kernel(
 template <typename T>
 __global__ __launch_bounds__(256) void bzifft_kernel(
     const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
-    int nitems, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
+    const int* __restrict__ qb, int* __restrict__ ctr, const cplx<T>* __restrict__ tw) {
     for (;;) {
-        const int it = next_item(ctr);
-        if (it >= nitems) return;
+        const int it = next_item(ctr, qb);
+        if (it < 0) return;
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
@@ -1938,11 +1949,11 @@ __global__ __launch_bounds__(256) void bzifft_kernel(
 template <typename T, int P>
 __global__ __launch_bounds__(64) void bgather_kernel(
     const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
-    int nitems, int* __restrict__ ctr, DevParticles<T> blk,
+    const int* __restrict__ qb, int* __restrict__ ctr, DevParticles<T> blk,
     T* __restrict__ phi_out, T* __restrict__ E_out) {
     for (;;) {
-        const int it = next_item(ctr);
-        if (it >= nitems) return;
+        const int it = next_item(ctr, qb);
+        if (it < 0) return;
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
@@ -1956,11 +1967,11 @@ __global__ __launch_bounds__(64) void bgather_kernel(
 template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void brealspace_kernel(
     const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
-    int nitems, int* __restrict__ ctr, DevParticles<T> blk,
+    const int* __restrict__ qb, int* __restrict__ ctr, DevParticles<T> blk,
     DevParticles<T> lx, T* __restrict__ phi_out, T* __restrict__ E_out) {
     for (;;) {
-        const int it = next_item(ctr);
-        if (it >= nitems) return;
+        const int it = next_item(ctr, qb);
+        if (it < 0) return;
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const Geo g = sd.g;
@@ -1975,13 +1986,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void br
 template <typename T>
 __global__ __launch_bounds__(kCombineThreads) void bcombine_kernel(
     const SysDesc<T>* __restrict__ sys, const Item* __restrict__ items,
-    int nitems, int* __restrict__ ctr, const T* __restrict__ q,
+    const int* __restrict__ qb, int* __restrict__ ctr, const T* __restrict__ q,
     const T* __restrict__ phiF, const T* __restrict__ EF,
     const T* __restrict__ phiR, const T* __restrict__ ER, unsigned flags,
     T* __restrict__ phi, T* __restrict__ E, double* __restrict__ partials) {
     for (;;) {
-        const int it = next_item(ctr);
-        if (it >= nitems) return;
+        const int it = next_item(ctr, qb);
+        if (it < 0) return;
         const Item w = items[it];
         const SysDesc<T>& sd = sys[w.sys];
         const unsigned f = sd.rs ? flags : (flags & ~2u);
@@ -2353,7 +2364,7 @@ static int batch_p(const BatchArgs<T>& a, const T* x, const T* q, T* phi,
     // counts and queue counters are cleared by kernels (no memset nodes if
     // the sequence is captured in a graph)
     if ((rc = bin_clear(a.bins, s))) return rc;
-    if ((rc = launch_fill_int(a.qctr, kNumQueues, 0, s))) return rc;
+    if ((rc = launch_fill_int(a.qctr, 8 * kQCtrStride * kNumQueues, 0, s))) return rc;
     hipLaunchKernelGGL(bbin_keys_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0, s,
                        x, N, a.sys_of, a.sys, a.bins);
     SE1P_CHECK_LAUNCH();
@@ -2369,40 +2380,39 @@ static int batch_p(const BatchArgs<T>& a, const T* x, const T* q, T* phi,
                            a.lex, N, a.sys_of, a.sys, a.wz, a.wxp, a.wyq);
         hipLaunchKernelGGL((bspread_kernel<T, P>), dim3(L[kQSpread].grid),
                            dim3(64 * spread_waves(P)), L[kQSpread].lds, s, a.sys, L[kQSpread].items,
-                           L[kQSpread].nitems, a.qctr + kQSpread, a.wz, a.wxp,
+                           L[kQSpread].qb, a.qctr + 8 * kQCtrStride * kQSpread, a.wz, a.wxp,
                            a.wyq, a.lex.cy, a.lex.start);
         SE1P_CHECK_LAUNCH();
         hipLaunchKernelGGL(bzfft_kernel<T>, dim3(L[kQZfft].grid), dim3(256),
                            L[kQZfft].lds, s, a.sys, L[kQZfft].items,
-                           L[kQZfft].nitems, a.qctr + kQZfft, a.tw);
+                           L[kQZfft].qb, a.qctr + 8 * kQCtrStride * kQZfft, a.tw);
         hipLaunchKernelGGL(browfwd_kernel<T>, dim3(L[kQRowFwd].grid), dim3(256),
                            L[kQRowFwd].lds, s, a.sys, L[kQRowFwd].items,
-                           L[kQRowFwd].nitems, a.qctr + kQRowFwd, a.tw);
+                           L[kQRowFwd].qb, a.qctr + 8 * kQCtrStride * kQRowFwd, a.tw);
         hipLaunchKernelGGL(bcols_kernel<T>, dim3(L[kQCols].grid), dim3(256),
                            L[kQCols].lds, s, a.sys, L[kQCols].items,
-                           L[kQCols].nitems, a.qctr + kQCols, a.tw);
+                           L[kQCols].qb, a.qctr + 8 * kQCtrStride * kQCols, a.tw);
         hipLaunchKernelGGL(browinv_kernel<T>, dim3(L[kQRowInv].grid), dim3(256),
                            L[kQRowInv].lds, s, a.sys, L[kQRowInv].items,
-                           L[kQRowInv].nitems, a.qctr + kQRowInv, a.tw);
+                           L[kQRowInv].qb, a.qctr + 8 * kQCtrStride * kQRowInv, a.tw);
         hipLaunchKernelGGL(bzifft_kernel<T>, dim3(L[kQZifft].grid), dim3(256),
                            L[kQZifft].lds, s, a.sys, L[kQZifft].items,
-                           L[kQZifft].nitems, a.qctr + kQZifft, a.tw);
+                           L[kQZifft].qb, a.qctr + 8 * kQCtrStride * kQZifft, a.tw);
         SE1P_CHECK_LAUNCH();
         hipLaunchKernelGGL((bgather_kernel<T, P>), dim3(L[kQGather].grid),
                            dim3(64), L[kQGather].lds, s, a.sys, L[kQGather].items,
-                           L[kQGather].nitems, a.qctr + kQGather, a.blk, a.phiF,
+                           L[kQGather].qb, a.qctr + 8 * kQCtrStride * kQGather, a.blk, a.phiF,
                            a.EF);
         SE1P_CHECK_LAUNCH();
     }
     if ((flags & 2u) && L[kQReal].nitems > 0) {
         hipLaunchKernelGGL(brealspace_kernel<T>, dim3(L[kQReal].grid), dim3(64),
-                           0, s, a.sys, L[kQReal].items, L[kQReal].nitems,
-                           a.qctr + kQReal, a.blk, a.lex, a.phiR, a.ER);
+                           0, s, a.sys, L[kQReal].items, L[kQReal].qb, a.qctr + 8 * kQCtrStride * kQReal, a.blk, a.lex, a.phiR, a.ER);
         SE1P_CHECK_LAUNCH();
     }
     hipLaunchKernelGGL(bcombine_kernel<T>, dim3(L[kQComb].grid),
                        dim3(kCombineThreads), 0, s, a.sys, L[kQComb].items,
-                       L[kQComb].nitems, a.qctr + kQComb, q, a.phiF, a.EF,
+                       L[kQComb].qb, a.qctr + 8 * kQCtrStride * kQComb, q, a.phiF, a.EF,
                        a.phiR, a.ER, flags & 7u, phi, E, a.partials);
     SE1P_CHECK_LAUNCH();
     if (energy) {
