@@ -1,18 +1,21 @@
 // se1p_kernels.hip -- HIP kernels of the SE1P k-space pipeline for gfx950.
 //
 // Pipeline (Algorithm 1 of the paper):
-//   bin        counting sort of the particles by cell in two orders
-//   spread     step 2, eq. spread_1p: owner-computes gridding, one wave per
-//              8 x 8 (x, y) pencil tile sweeping a chunk of z cells with the
-//              z-support in registers; per-particle z weights arrive as
+//   bin        counting sort of the particles by cell in two orders (cell
+//              counts, a reduce-then-scan, placement by rank of the input
+//              index inside a cell)
+//   spread     step 2, eq. spread_1p: owner-computes gridding, a workgroup
+//              of 1 to 8 waves per 8 x 8 (x, y) pencil tile sweeping a chunk
+//              of z cells with the z-support in registers; the waves share
+//              each z cell's particle list; per-particle z weights arrive as
 //              wave-uniform (scalar) loads, x/y weights are per lane
 //   kspace     steps 3-5: z FFT (real, two columns per complex transform),
 //              per-slab zero-padded row FFTs, fused column FFT -> scaling
 //              (eq. scale_1p with G of eq. G_kappa_k) -> inverse column FFT,
 //              inverse row FFTs, inverse z FFT; Stockham FFTs in LDS
 //   gather     step 6 (eq. se1p_complete_discretized) and its analytic
-//              gradient (eq. force_se1p): one lane per particle, grid rows
-//              read as wave-uniform scalar loads
+//              gradient (eq. force_se1p): one lane per particle, the grid
+//              planes a chunk's supports touch staged in LDS
 //   realspace  eq. ewald1p_real / eq. force_real over the cell list
 //   combine    totals, self term (eq. ewald1p_self), energy 1/2 sum q phi
 //
@@ -1315,8 +1318,10 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
 }
 
 // exp(y) for -708 < y <= 0: y = k ln2 + r with |r| <= ln2/2 (Cody-Waite
-// split of ln2), exp(r) by its Taylor series to degree 9 (truncation below
-// 7e-12 relative, the size of the erfcx fit's error), scaled by 2^k.
+// reduction, with ln2 split into the two parts published with Sun's fdlibm
+// exp, whose high part carries few enough bits that k ln2_hi is exact),
+// exp(r) by its Taylor series to degree 9 (truncation below 7e-12 relative,
+// the size of the erfcx fit's error), scaled by 2^k.
 __device__ __forceinline__ double exp_neg(double y) {
     const double k = rint(y * 1.4426950408889634074);
     double r = fma3(-k, 6.93147180369123816490e-01, y);
