@@ -988,8 +988,20 @@ __device__ __forceinline__ void cols_body(
 template <typename T>
 __global__ __launch_bounds__(256) void cols_kernel(
     cplx<T>* __restrict__ G, const SlabDesc* __restrict__ slabs, Geo g,
-    const cplx<T>* __restrict__ tw, const T* __restrict__ S0, int dir) {
-    cols_body<T>(G, slabs, g, tw, S0, blockIdx.x, blockIdx.y, kColsPerBlock, dir);
+    const cplx<T>* __restrict__ tw, const T* __restrict__ S0, int dir,
+    unsigned ncblk, int nslab) {
+    // The column blocks that share a 128-byte line of every row (GL of
+    // them) run on one XCD, and these groups are dealt round robin to the
+    // XCDs (the dispatcher deals blocks to XCD index % 8), so heavy slabs
+    // still spread over the chip.  The grid is padded to a multiple of
+    // 8 GL blocks; blocks mapped past the end return.
+    constexpr int GL = 128 / (kColsPerBlock * 2 * (int)sizeof(T));
+    const unsigned L = blockIdx.x + gridDim.x * blockIdx.y;
+    const unsigned r = L % 8, m = L / 8;
+    const unsigned idx = ((m / GL) * 8 + r) * GL + m % GL;
+    if (idx >= ncblk * (unsigned)nslab) return;
+    cols_body<T>(G, slabs, g, tw, S0, (int)(idx % ncblk), (int)(idx / ncblk),
+                 kColsPerBlock, dir);
 }
 
 // Inverse FFT along y, restriction to the first Mt2 columns.
@@ -2019,6 +2031,15 @@ __global__ __launch_bounds__(256) void benergy_kernel(
 
 inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Grid of the column pass: ncblk x nslab blocks padded to a multiple of
+// 8 GL (cols_kernel maps dispatch index to block).
+template <typename T>
+dim3 cols_grid(unsigned ncblk, int nslab) {
+    const unsigned gl = 128u / (kColsPerBlock * 2u * (unsigned)sizeof(T));
+    const unsigned n = ncblk * (unsigned)nslab, q = 8u * gl;
+    return dim3((n + q - 1) / q * q);
+}
+
 }  // namespace
 
 // ==========================================================================
@@ -2143,9 +2164,10 @@ int launch_kspace(const T* Hin, int KP, long long pstride, T in_scale,
                        d_slabs, g, tw);
     SE1P_CHECK_LAUNCH();
     const size_t csm = 2 * (size_t)kColsPerBlock * (n1max + 1) * cs;
-    dim3 cgrid((n2max + kColsPerBlock - 1) / kColsPerBlock, nslab);
+    const unsigned ncblk = (unsigned)((n2max + kColsPerBlock - 1) / kColsPerBlock);
+    const dim3 cgrid = cols_grid<T>(ncblk, nslab);
     hipLaunchKernelGGL(cols_kernel<T>, cgrid, dim3(256), csm, s, G, d_slabs, g,
-                       tw, S0, -1);
+                       tw, S0, -1, ncblk, nslab);
     SE1P_CHECK_LAUNCH();
     hipLaunchKernelGGL(rowinv_kernel<T>, rgrid, dim3(256), rsm, s, G, Fz,
                        d_slabs, g, tw);
@@ -2188,12 +2210,13 @@ int launch_kspace_ik(const T* Hin, int KP, long long pstride, const Geo& g,
                            hipMemcpyDeviceToDevice, s) != hipSuccess)
             return -5;
     const size_t csm = 2 * (size_t)kColsPerBlock * (n1max + 1) * cs;
-    dim3 cgrid((n2max + kColsPerBlock - 1) / kColsPerBlock, nslab);
+    const unsigned ncblk = (unsigned)((n2max + kColsPerBlock - 1) / kColsPerBlock);
+    const dim3 cgrid = cols_grid<T>(ncblk, nslab);
     for (int d = -1; d < 3; ++d) {
         cplx<T>* Gd = d < 0 ? G : Gk + d * slab_elems;
         T* Hd = d < 0 ? Ht : Htk + d * gstride;
         hipLaunchKernelGGL(cols_kernel<T>, cgrid, dim3(256), csm, s, Gd, d_slabs, g,
-                           tw, S0, d);
+                           tw, S0, d, ncblk, nslab);
         SE1P_CHECK_LAUNCH();
         hipLaunchKernelGGL(rowinv_kernel<T>, rgrid, dim3(256), rsm, s, Gd, Fz,
                            d_slabs, g, tw);
