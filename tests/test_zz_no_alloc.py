@@ -114,3 +114,44 @@ def test_noalloc_rejects_oversize_on_the_host():
     assert rc == se1p.ERR_SCRATCH
     assert b"static" in se1p._lib().se1p_error_string(rc)
     plan.close()
+
+
+def test_noalloc_replays_in_a_hip_graph():
+    """The reason for the entry point: a caller that captures the evaluation
+    in a HIP graph (no allocation may happen while capturing).  The graph is
+    replayed several times with other device work and synchronisations in
+    between, each replay checked bit for bit against the eager call (the
+    same kernels on the same inputs)."""
+    from paper_1611_09538_amd import se1p
+    dev = _dev()
+    n = 500
+    plan, c = _plan("small", n)
+    x, q, box, _ = workloads.make_case("small", n=n, seed=91)
+    xt = torch.tensor(x, device=dev)
+    qt = torch.tensor(q, device=dev)
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    E = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    U = torch.empty(1, dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.eval_noalloc_into(xt, qt, phi, E, U)        # first call: symbol lookup
+        torch.cuda.synchronize()
+        ref = (phi.clone(), E.clone(), U.clone())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            plan.eval_noalloc_into(xt, qt, phi, E, U)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for k in range(4):
+        phi.fill_(float("nan"))
+        E.fill_(float("nan"))
+        U.fill_(float("nan"))
+        junk = torch.randn(1 << 16, device=dev).sum()      # other device work
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _say(f"replay {k}: max |dphi| {float((phi - ref[0]).abs().max()):.1e}")
+        assert torch.equal(phi, ref[0]) and torch.equal(E, ref[1]) and torch.equal(U, ref[2])
+        del junk
+    plan.close()
