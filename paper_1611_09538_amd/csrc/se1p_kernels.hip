@@ -278,14 +278,15 @@ __device__ __forceinline__ void cell_keys(const T* __restrict__ xin, long long i
     kb = b * bg.cpb + (izs * bg.BX + ix) * bg.BY + iy;
 }
 
-// Records the cell keys of particle i, takes its arrival slot in its lex
-// cell and counts it in the cells of both orders.
+// Records the cell keys of particle i and takes its arrival slot in its lex
+// cell; with blk_count it is also counted in its block-order cell (the
+// batch, whose block-order counts are not derived from the lex counts).
 __device__ __forceinline__ void count_keys(long long i, int kl, int kb,
-                                           const BinBufs& b) {
+                                           const BinBufs& b, bool blk_count) {
     b.key_lex[i] = kl;
     b.key_blk[i] = kb;
     b.slot[i] = atomicAdd(&b.cnt_lex[kl], 1);
-    atomicAdd(&b.cnt_blk[kb], 1);
+    if (blk_count) atomicAdd(&b.cnt_blk[kb], 1);
 }
 
 template <typename T>
@@ -295,13 +296,13 @@ __global__ void bin_keys_kernel(const T* __restrict__ xin, long long N, Geo g,
     if (i >= N) return;
     int kl, kb;
     cell_keys<T>(xin, i, g, bg, kl, kb);
-    count_keys(i, kl, kb, b);
+    count_keys(i, kl, kb, b, false);
 }
 
-// Zeroes the cell counts of both orders.
-__global__ void bin_clear_kernel(BinBufs b) {
+// Zeroes the lex cell counts and, with both, the block-order ones.
+__global__ void bin_clear_kernel(BinBufs b, bool both) {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long n1 = b.ncl + 1, n2 = b.ncb + 1;
+    const long long n1 = b.ncl + 1, n2 = both ? b.ncb + 1 : 0;
     if (k < n1) b.cnt_lex[k] = 0;
     else if (k < n1 + n2) b.cnt_blk[k - n1] = 0;
 }
@@ -320,13 +321,59 @@ __device__ __forceinline__ int wave_incl_scan_int(int v) {
 }
 
 // Exclusive scan of n counts into starts (start[k] = sum of cnt[0..k)).
+// With lexcnt set, the counts are those of the block-order cells, taken
+// from the lex counts of the same cells by the first pass (which writes
+// them to cnt for the second).
 struct ScanJob {
-    const int* cnt;
+    int* cnt;
     int* start;
     long long n;
     const int* tsum;   // particles per tile of kScanTile counts
     int ntiles;
+    const int* lexcnt;
+    BinGeo bg;
+    int M1, M2;
 };
+
+// Lex counts of the block-order cells [k, k + kScanItems) (cells past the
+// grid, in blocks that overhang it, and the end entry count zero).  The
+// cell indices are decoded once and then stepped: y fastest, then x, then
+// the block's z layer (counted backwards in odd blocks), then the block.
+__device__ __forceinline__ void blk_counts_from_lex(const ScanJob& j, long long k,
+                                                    int (&v)[kScanItems]) {
+    const BinGeo& bg = j.bg;
+    const long long ncb = j.n - 1;
+    const int bxy = bg.BX * bg.BY;
+    int b = (int)(k / bg.cpb);
+    const int rem = (int)(k - (long long)b * bg.cpb);
+    int izs = rem / bxy;
+    int ix = (rem - izs * bxy) / bg.BY;
+    int iy = rem - izs * bxy - ix * bg.BY;
+    int bz = 0, bx = 0, by = 0;
+    if (k < ncb) block_coords(b, bg, bz, bx, by);
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        int c = 0;
+        if (k + t < ncb) {
+            const int iz = (b & 1) ? bg.BZ - 1 - izs : izs;
+            const int cz = bz * bg.BZ + iz, cx = bx * bg.BX + ix, cy = by * bg.BY + iy;
+            if (cx < j.M1 && cy < j.M2)
+                c = j.lexcnt[((long long)cz * j.M1 + cx) * j.M2 + cy];
+            if (++iy == bg.BY) {
+                iy = 0;
+                if (++ix == bg.BX) {
+                    ix = 0;
+                    if (++izs == bg.BZ) {
+                        izs = 0;
+                        ++b;
+                        if (k + t + 1 < ncb) block_coords(b, bg, bz, bx, by);
+                    }
+                }
+            }
+        }
+        v[t] = c;
+    }
+}
 
 // Loads the kScanItems counts of thread tid of tile t (zeros past n).
 __device__ __forceinline__ bool scan_load(const ScanJob& j, int t, int tid,
@@ -357,7 +404,20 @@ __global__ __launch_bounds__(256) void bin_tile_sum_kernel(ScanJob a, ScanJob b,
     const ScanJob j = second ? b : a;
     if (second) t -= a.ntiles;
     int v[kScanItems];
-    scan_load(j, t, threadIdx.x, v);
+    if (j.lexcnt) {
+        const long long base = (long long)t * kScanTile + (long long)threadIdx.x * kScanItems;
+        if (base < j.n) {
+            blk_counts_from_lex(j, base, v);
+#pragma unroll
+            for (int k = 0; k < kScanItems; ++k)
+                if (base + k < j.n) j.cnt[base + k] = v[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < kScanItems; ++k) v[k] = 0;
+        }
+    } else {
+        scan_load(j, t, threadIdx.x, v);
+    }
     int tot = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) tot += v[k];
@@ -417,12 +477,16 @@ __global__ __launch_bounds__(256) void bin_scan_kernel(ScanJob a, ScanJob b) {
     }
 }
 
-// Lex order by arrival: particle i at its cell start plus its slot.
+// Lex order by arrival: particle i at its cell start plus its slot (only
+// in cells of two or more particles: alone in its cell a particle's rank
+// is 0 without it).
 __global__ void bin_scatter_kernel(long long N, BinBufs b,
                                    const int* __restrict__ start) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    b.tmp[start[b.key_lex[i]] + b.slot[i]] = (int)i;
+    const int kl = b.key_lex[i];
+    const int s = start[kl];
+    if (start[kl + 1] - s > 1) b.tmp[s + b.slot[i]] = (int)i;
 }
 
 // Final positions: inside its cell a particle takes the rank of its input
@@ -440,7 +504,8 @@ __global__ void bin_rank_kernel(long long N, BinBufs b,
     const int kl = b.key_lex[i];
     const int s = lex_start[kl], e = lex_start[kl + 1];
     int r = 0;
-    for (int k = s; k < e; ++k) r += b.tmp[k] < (int)i;
+    if (e - s > 1)
+        for (int k = s; k < e; ++k) r += b.tmp[k] < (int)i;
     lex_perm[s + r] = (int)i;
     blk_perm[blk_start[b.key_blk[i]] + r] = (int)i;
 }
@@ -483,9 +548,12 @@ __global__ void bin_gather_kernel(const T* __restrict__ xin,
 // ------------------------------------------------------------------------
 // Per particle (lex order): z weights wz[P] (wave-uniform in the spread
 // kernel) and x weights wxp[PW], q * y weights wyq[PW], PW = P + 2 pad with
-// pad = weight_pad(sizeof(T)) zeros on each side.  One weight per thread, so
-// that the stores are coalesced: elements [0, N PW) are wxp, [N PW, 2 N PW)
-// wyq and [2 N PW, 2 N PW + N P) wz.
+// pad = weight_pad(sizeof(T)) zeros on each side.
+//
+// FP64: one weight per thread, each from its own exponential, so that the
+// stores are coalesced: elements [0, N PW) are wxp, [N PW, 2 N PW) wyq and
+// [2 N PW, 2 N PW + N P) wz.  (One row per thread with the Gaussian
+// recurrence was slower here: 3N threads of long dependent chains.)
 template <typename T, int P>
 constexpr long long spread_weight_count(long long N) {
     return N * (2 * (P + 2 * weight_pad((int)sizeof(T))) + P);
@@ -498,6 +566,7 @@ __device__ __forceinline__ void spread_weight_elem(const DevParticles<T>& lx,
                                                    T* __restrict__ wz,
                                                    T* __restrict__ wxp,
                                                    T* __restrict__ wyq) {
+    static_assert(sizeof(T) == 8, "FP32 weights are written one row per thread");
     constexpr int pad = weight_pad((int)sizeof(T));
     constexpr int PW = P + 2 * pad;
     const T h = (T)g.h, a = (T)g.alpha;
@@ -511,13 +580,8 @@ __device__ __forceinline__ void spread_weight_elem(const DevParticles<T>& lx,
         T w = 0;
         if (u >= 0 && u < P) {
             const T t = isy ? lx.ty[p] : lx.tx[p];
-            if constexpr (sizeof(T) == 4) {
-                const GaussC gc = gauss_consts(g);
-                w = gauss_u(t - (T)(1 + u - P / 2), gc.hi, gc.lo);
-            } else {
-                const T d = (t - (T)(1 + u - P / 2)) * h;
-                w = dexp<T>(-a * d * d);
-            }
+            const T d = (t - (T)(1 + u - P / 2)) * h;
+            w = dexp<T>(-a * d * d);
             if (isy) w = lx.q[p] * w;
         }
         (isy ? wyq : wxp)[j] = w;
@@ -525,13 +589,68 @@ __device__ __forceinline__ void spread_weight_elem(const DevParticles<T>& lx,
         const long long j = i - 2 * nxy;
         const long long p = j / P;
         const int d = (int)(j - p * P);
-        if constexpr (sizeof(T) == 4) {
-            const GaussC gc = gauss_consts(g);
-            wz[j] = gauss_u(lx.tz[p] - (T)(1 + d - P / 2), gc.hi, gc.lo);
-        } else {
-            const T dz = (lx.tz[p] - (T)(1 + d - P / 2)) * h;
-            wz[j] = dexp<T>(-a * dz * dz);
-        }
+        const T dz = (lx.tz[p] - (T)(1 + d - P / 2)) * h;
+        wz[j] = dexp<T>(-a * dz * dz);
+    }
+}
+
+// FP32: one row per thread, threads [0, N) the x rows, [N, 2N) the y rows,
+// [2N, 3N) the z rows (a wave's branch is uniform), every weight from its
+// own offset in units of h, the row stored in 8-byte pieces.
+template <int P>
+__device__ __forceinline__ void spread_weight_row(const DevParticles<float>& lx,
+                                                  long long p, int axis,
+                                                  const Geo& g,
+                                                  float* __restrict__ wz,
+                                                  float* __restrict__ wxp,
+                                                  float* __restrict__ wyq) {
+    static_assert(weight_pad(4) == 0, "FP32 weight rows carry no padding");
+    // offset in the cell in units of h; window point u is grid index
+    // c + 1 + u - P/2 (c the particle's cell)
+    const float t = axis == 0 ? lx.tx[p] : (axis == 1 ? lx.ty[p] : lx.tz[p]);
+    const GaussC gc = gauss_consts(g);
+    const float qp = axis == 1 ? lx.q[p] : 1.0f;
+    float w[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) w[u] = gauss_u(t - (float)(1 + u - P / 2), gc.hi, gc.lo);
+    if (axis == 1) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) w[u] *= qp;
+    }
+    float2* dst = reinterpret_cast<float2*>((axis == 0 ? wxp : axis == 1 ? wyq : wz) + p * P);
+#pragma unroll
+    for (int u = 0; u < P; u += 2) dst[u / 2] = make_float2(w[u], w[u + 1]);
+}
+
+// Threads of the weight kernel for N particles.
+template <typename T, int P>
+constexpr long long spread_weight_threads(long long N) {
+    return sizeof(T) == 8 ? spread_weight_count<T, P>(N) : 3 * N;
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void spread_weight_thread(const DevParticles<T>& lx,
+                                                     long long N, long long i,
+                                                     const Geo& g, T* __restrict__ wz,
+                                                     T* __restrict__ wxp,
+                                                     T* __restrict__ wyq) {
+    if constexpr (sizeof(T) == 8) {
+        spread_weight_elem<T, P>(lx, N, i, g, wz, wxp, wyq);
+    } else {
+        const int axis = (int)(i / N);
+        spread_weight_row<P>(lx, i - axis * N, axis, g, wz, wxp, wyq);
+    }
+}
+
+// Particle of weight-kernel thread i.
+template <typename T, int P>
+__device__ __forceinline__ long long spread_weight_particle(long long N, long long i) {
+    if constexpr (sizeof(T) == 8) {
+        constexpr int PW = P + 2 * weight_pad(8);
+        const long long nxy = N * PW;
+        return i < 2 * nxy ? (i % nxy) / PW : (i - 2 * nxy) / P;
+    } else {
+        return i % N;
     }
 }
 
@@ -540,8 +659,8 @@ __global__ void spread_weights_kernel(DevParticles<T> lx, long long N, Geo g,
                                       T* __restrict__ wz, T* __restrict__ wxp,
                                       T* __restrict__ wyq) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= spread_weight_count<T, P>(N)) return;
-    spread_weight_elem<T, P>(lx, N, i, g, wz, wxp, wyq);
+    if (i >= spread_weight_threads<T, P>(N)) return;
+    spread_weight_thread<T, P>(lx, N, i, g, wz, wxp, wyq);
 }
 
 // A workgroup of spread_waves(P) waves owns the (x, y) pencils [X0, X0+8) x
@@ -1845,7 +1964,7 @@ __global__ void bbin_keys_kernel(const T* __restrict__ xin, long long N,
     const SysDesc<T>& sd = sys[sys_of[i]];
     int kl, kb;
     cell_keys<T>(xin, i, sd.g, sd.bg, kl, kb);
-    count_keys(i, kl + (int)sd.cl0, kb + (int)sd.cb0, b);
+    count_keys(i, kl + (int)sd.cl0, kb + (int)sd.cb0, b, true);
 }
 
 // Sorted position p belongs to the same system as its input index.
@@ -1869,11 +1988,9 @@ __global__ void bspread_weights_kernel(DevParticles<T> lx, long long N,
                                        T* __restrict__ wz, T* __restrict__ wxp,
                                        T* __restrict__ wyq) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= spread_weight_count<T, P>(N)) return;
-    constexpr int PW = P + 2 * weight_pad((int)sizeof(T));
-    const long long nxy = N * PW;
-    const long long p = i < 2 * nxy ? (i % nxy) / PW : (i - 2 * nxy) / P;
-    spread_weight_elem<T, P>(lx, N, i, sys[sys_of[p]].g, wz, wxp, wyq);
+    if (i >= spread_weight_threads<T, P>(N)) return;
+    const long long p = spread_weight_particle<T, P>(N, i);
+    spread_weight_thread<T, P>(lx, N, i, sys[sys_of[p]].g, wz, wxp, wyq);
 }
 
 template <typename T, int P>
@@ -2060,17 +2177,23 @@ int launch_fill_int(int* p, long long n, int v, hipStream_t s) {
 
 // Clears the counts, then (after the key kernel has counted) scans both
 // orders, places the particles by arrival and then by rank.
-static int bin_clear(const BinBufs& b, hipStream_t s) {
-    const long long n = b.ncl + 1 + b.ncb + 1;
-    hipLaunchKernelGGL(bin_clear_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, b);
+// both: clear the block-order counts too (the batch counts them by atomics;
+// one system derives them from the lex counts).
+static int bin_clear(const BinBufs& b, bool both, hipStream_t s) {
+    const long long n = b.ncl + 1 + (both ? b.ncb + 1 : 0);
+    hipLaunchKernelGGL(bin_clear_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, b, both);
     SE1P_CHECK_LAUNCH();
     return 0;
 }
 
+// bg, M1, M2 null / unused: block-order counts already in cnt_blk (batch);
+// else taken from the lex counts of the one system's grid.
 static int bin_sort(long long N, const BinBufs& b, int* lex_start, int* blk_start,
-                    int* lex_perm, int* blk_perm, hipStream_t s) {
-    const ScanJob ja{b.cnt_lex, lex_start, b.ncl + 1, b.tsum, b.ntl};
-    const ScanJob jb{b.cnt_blk, blk_start, b.ncb + 1, b.tsum + b.ntl, b.ntb};
+                    int* lex_perm, int* blk_perm, hipStream_t s,
+                    const BinGeo* bg = nullptr, int M1 = 0, int M2 = 0) {
+    const ScanJob ja{b.cnt_lex, lex_start, b.ncl + 1, b.tsum, b.ntl, nullptr, BinGeo{}, 0, 0};
+    const ScanJob jb{b.cnt_blk, blk_start, b.ncb + 1, b.tsum + b.ntl, b.ntb,
+                     bg ? b.cnt_lex : nullptr, bg ? *bg : BinGeo{}, M1, M2};
     hipLaunchKernelGGL(bin_tile_sum_kernel, dim3(b.ntl + b.ntb), dim3(256), 0, s, ja, jb,
                        b.tsum);
     hipLaunchKernelGGL(bin_scan_kernel, dim3(b.ntl + b.ntb), dim3(256), 0, s, ja, jb);
@@ -2089,11 +2212,12 @@ int launch_bin(const T* x_in, const T* q_in, long long N, const Geo& g,
     // counting sort into the lex and block orders (the block order numbers
     // the same cells, so both share each particle's rank in its cell)
     int rc;
-    if ((rc = bin_clear(b, s))) return rc;
+    if ((rc = bin_clear(b, false, s))) return rc;
     hipLaunchKernelGGL(bin_keys_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0, s,
                        x_in, N, g, bg, b);
     SE1P_CHECK_LAUNCH();
-    if ((rc = bin_sort(N, b, lex.start, blk.start, lex.perm, blk.perm, s))) return rc;
+    if ((rc = bin_sort(N, b, lex.start, blk.start, lex.perm, blk.perm, s, &bg, g.M1, g.M2)))
+        return rc;
     hipLaunchKernelGGL(bin_gather_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0,
                        s, x_in, q_in, N, g, lex, blk);
     SE1P_CHECK_LAUNCH();
@@ -2105,7 +2229,7 @@ static int spread_p(const DevParticles<T>& lex, long long N, const Geo& g,
                     int CZ, int KP, T* wz, T* wxp, T* wyq, T* Hpart,
                     long long pstride, hipStream_t s) {
     hipLaunchKernelGGL((spread_weights_kernel<T, P>),
-                       dim3(nblk(spread_weight_count<T, P>(N), 256)), dim3(256), 0, s,
+                       dim3(nblk(spread_weight_threads<T, P>(N), 256)), dim3(256), 0, s,
                        lex, N, g, wz, wxp, wyq);
     SE1P_CHECK_LAUNCH();
     dim3 grid((g.Mt1 + kSpreadTile - 1) / kSpreadTile,
@@ -2391,7 +2515,7 @@ static int batch_p(const BatchArgs<T>& a, const T* x, const T* q, T* phi,
     int rc;
     // counts and queue counters are cleared by kernels (no memset nodes if
     // the sequence is captured in a graph)
-    if ((rc = bin_clear(a.bins, s))) return rc;
+    if ((rc = bin_clear(a.bins, true, s))) return rc;
     if ((rc = launch_fill_int(a.qctr, 8 * kQCtrStride * kNumQueues, 0, s))) return rc;
     hipLaunchKernelGGL(bbin_keys_kernel<T>, dim3(nblk(N, 256)), dim3(256), 0, s,
                        x, N, a.sys_of, a.sys, a.bins);
@@ -2404,7 +2528,7 @@ static int batch_p(const BatchArgs<T>& a, const T* x, const T* q, T* phi,
     const BatchLaunch* L = a.q;
     if (flags & 1u) {
         hipLaunchKernelGGL((bspread_weights_kernel<T, P>),
-                           dim3(nblk(spread_weight_count<T, P>(N), 256)), dim3(256), 0, s,
+                           dim3(nblk(spread_weight_threads<T, P>(N), 256)), dim3(256), 0, s,
                            a.lex, N, a.sys_of, a.sys, a.wz, a.wxp, a.wyq);
         hipLaunchKernelGGL((bspread_kernel<T, P>), dim3(L[kQSpread].grid),
                            dim3(64 * spread_waves(P)), L[kQSpread].lds, s, a.sys, L[kQSpread].items,
