@@ -1451,22 +1451,16 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
 // exp(y) for -708 < y <= 0: y = k ln2 + r with |r| <= ln2/2 (Cody-Waite
 // reduction, with ln2 split into the two parts published with Sun's fdlibm
 // exp, whose high part carries few enough bits that k ln2_hi is exact),
-// exp(r) by its Taylor series to degree 9 (truncation below 7e-12 relative,
-// the size of the erfcx fit's error), scaled by 2^k.
+// exp(r) by a degree-8 Chebyshev fit on [-ln2/2, ln2/2] (3e-12 relative,
+// below the erfcx fit's error; the Taylor series needs degree 9 for that),
+// scaled by 2^k.
 __device__ __forceinline__ double exp_neg(double y) {
     const double k = rint(y * 1.4426950408889634074);
     double r = fma3(-k, 6.93147180369123816490e-01, y);
     r = fma3(-k, 1.90821492927058770002e-10, r);
-    double p = 1.0 / 362880.0;                        // 1/9!
-    p = fma3(p, r, 1.0 / 40320.0);
-    p = fma3(p, r, 1.0 / 5040.0);
-    p = fma3(p, r, 1.0 / 720.0);
-    p = fma3(p, r, 1.0 / 120.0);
-    p = fma3(p, r, 1.0 / 24.0);
-    p = fma3(p, r, 1.0 / 6.0);
-    p = fma3(p, r, 0.5);
-    p = fma3(p, r, 1.0);
-    p = fma3(p, r, 1.0);
+    double p = kExpC[kExpDeg];
+#pragma unroll
+    for (int j = kExpDeg - 1; j >= 0; --j) p = fma3(p, r, kExpC[j]);
     return ldexp(p, (int)k);
 }
 
@@ -1489,9 +1483,10 @@ __device__ __forceinline__ void pair_terms<double>(double r2, double xi,
     const double r = r2 * rinv;
     const double x = fmin(xi * r, kErfcxXmax);
     const double e = exp_neg(-xi2 * r2);
+    // hardware reciprocal (about 23 bits) and one Newton step: 1 / den to
+    // about 2^-46, far below the fit's error (den is in [1, 1 + 8 A])
     const double den = 1.0 + kErfcxA * x;
     double t = __builtin_amdgcn_rcp(den);
-    t = t * (2.0 - den * t);
     t = t * (2.0 - den * t);
     const double cu = 2.0 / (1.0 - kErfcxTmin);
     const double u = fma(t, cu, -1.0 - kErfcxTmin * cu);
@@ -1575,21 +1570,30 @@ __device__ __forceinline__ void realspace_body(
         auto pop = [&](int old_slot, bool drain) {
             // bit b < 16: candidate kq + 4 b of the older slot; b >= 16:
             // candidate kq + 4 (b - 16) of the newer one
-            while (__any(drain ? mask != 0u : (mask & 0xFFFFu) != 0u)) {
-                if (mask != 0u) {
-                    const int j = (kq + 4 * __builtin_ctz(mask) + 64 * old_slot) & 127;
-                    mask &= mask - 1u;
-                    const T dx = xt - cx_[j], dy = yt - cy_[j], dz = zt - cz_[j];
-                    const T r2 = dx * dx + dy * dy + dz * dz;
-                    const T qn = cq_[j];
-                    T ec, f;
-                    pair_terms<T>(r2, xi, xi2, c_erf, qn, ec, f);
-                    phi += qn * ec;
-                    ex += f * dx;
-                    ey += f * dy;
-                    ez += f * dz;
-                }
+            // every pass pops one bit per lane, lowest (oldest) first, so
+            // the pass count is the largest count of the bits to consume
+            int np = __popc(drain ? mask : (mask & 0xFFFFu));
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) np = max(np, __shfl_xor(np, m));
+            np = __builtin_amdgcn_readfirstlane(np);
+            for (int it = 0; it < np; ++it) {
+                const bool has = mask != 0u;
+                const int b = has ? __builtin_ctz(mask) : 0;
+                const int j = (kq + 4 * b + 64 * old_slot) & 127;
+                mask &= mask - 1u;
+                const T dx = xt - cx_[j], dy = yt - cy_[j], dz = zt - cz_[j];
+                const T r2v = dx * dx + dy * dy + dz * dz;
+                const T qv = cq_[j];
+                const T r2 = has ? r2v : (T)1;
+                const T qn = has ? qv : (T)0;
+                T ec, f;
+                pair_terms<T>(r2, xi, xi2, c_erf, qn, ec, f);
+                phi = fma(qn, ec, phi);
+                ex = fma(f, dx, ex);
+                ey = fma(f, dy, ey);
+                ez = fma(f, dz, ez);
             }
+
         };
         auto process = [&](int n, int slot) {
             // pass 1: one bit per in-range candidate j = kq + 4 i
