@@ -1184,7 +1184,7 @@ __device__ __forceinline__ void gather_body(
     int phi_stride = 1) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
-    constexpr int HP = P / 2;         // the y window is swept in two halves
+    constexpr int HP = P / 2;         // rows are read from LDS in two halves
     const int b = bid / CH;
     const int slot = bid - b * CH;
     int bzk, bxk, byk;
@@ -1231,16 +1231,13 @@ __device__ __forceinline__ void gather_body(
         const T dx0 = (tx - (T)(1 - P / 2)) * h;
         const T dy0 = (ty - (T)(1 - P / 2)) * h;
         // Gaussian-gridding recurrence seeds (FP64): value and ratio at the
-        // window start and at the start of the second half in y
-        T wx0 = 0, rx0 = 0, wyA = 0, ryA = 0, wyB = 0, ryB = 0;
+        // window start
+        T wx0 = 0, rx0 = 0, wyA = 0, ryA = 0;
         if constexpr (sizeof(T) == 8) {
             wx0 = dexp<T>(-a * dx0 * dx0);
             rx0 = dexp<T>(a * h * ((T)2 * dx0 - h));
             wyA = dexp<T>(-a * dy0 * dy0);
             ryA = dexp<T>(a * h * ((T)2 * dy0 - h));
-            const T dyB = dy0 - (T)HP * h;
-            wyB = dexp<T>(-a * dyB * dyB);
-            ryB = dexp<T>(a * h * ((T)2 * dyB - h));
         }
         T phi = 0, ex = 0, ey = 0, ez = 0;
         // FP32: every weight of the particle once, from offsets in units of
@@ -1265,7 +1262,22 @@ __device__ __forceinline__ void gather_body(
             }
         }
 
+        // FP64: the y weights of the whole window, once per particle (the
+        // Gaussian recurrence from the window's first point)
+        [[maybe_unused]] T wyw[sizeof(T) == 8 ? P : 1], tyw[sizeof(T) == 8 ? P : 1];
+        if constexpr (sizeof(T) == 8) {
+            T w = wyA, rr = ryA;
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                wyw[u] = w;
+                tyw[u] = (dy0 - (T)u * h) * w;
+                w *= rr;
+                rr *= C2;
+            }
+        }
+
         // Planes stream straight from global memory into LDS (16-byte
+
         // global_load_lds chunks, 64 per instruction), one plane ahead of
         // the plane being read.
         auto stage = [&](int ip, T* buf) {
@@ -1333,59 +1345,42 @@ __device__ __forceinline__ void gather_body(
             // lanes are sorted by z, so at the first and last planes whole
             // groups of lanes are idle and issue no LDS reads
             if (sizeof(T) == 8 && zin) {
+                // whole rows (2 P FMAs each), summed over the plane with
+                // the x weights, then scaled by the z weight once
+                const T* base = cur + ox * ldy + oy;
+                T wrec = wx0, rrec = rx0;
+                T sp = 0, spx = 0, spy = 0;
+                for (int dx = 0; dx < P; ++dx) {
+                    const T wx = wrec;
+                    wrec *= rrec;
+                    rrec *= C2;
+                    const T* row = base + dx * ldy;
+                    T sy = 0, sty = 0;
 #pragma unroll
-                for (int half = 0; half < 2; ++half) {
-                    // y weights of this half of the window (registers)
-                    T wy[HP], ty[HP];
-                    {
-                        T w = half ? wyB : wyA, rr = half ? ryB : ryA;
-#pragma unroll
-                        for (int u = 0; u < HP; ++u) {
-                            const T dy = dy0 - (T)(half * HP + u) * h;
-                            T wu;
-                            if constexpr (sizeof(T) == 8) {
-                                wu = w;
-                                w *= rr;
-                                rr *= C2;
-                            } else {
-                                wu = dexp<T>(-a * dy * dy);
-                            }
-                            wy[u] = wu;
-                            ty[u] = dy * wu;
-                        }
-                    }
-                    const T* base = cur + ox * ldy + oy + half * HP;
-                    T wrec = wx0, rrec = rx0;
-                    for (int dx = 0; dx < P; ++dx) {
-                        T wx;
-                        const T ddx = dx0 - (T)dx * h;
-                        if constexpr (sizeof(T) == 8) {
-                            wx = wrec;
-                            wrec *= rrec;
-                            rrec *= C2;
-                        } else {
-                            wx = dexp<T>(-a * ddx * ddx);
-                        }
-                        const T* row = base + dx * ldy;
+                    for (int u0 = 0; u0 < P; u0 += HP) {
                         T hv[HP];
 #pragma unroll
-                        for (int u = 0; u < HP; ++u) hv[u] = row[u];
-                        T sy = 0, sty = 0;
+                        for (int u = 0; u < HP; ++u) hv[u] = row[u0 + u];
 #pragma unroll
                         for (int u = 0; u < HP; ++u) {
-                            sy = fma(wy[u], hv[u], sy);
-                            if constexpr (FIELD) sty = fma(ty[u], hv[u], sty);
-                        }
-                        const T wxz = wx * wzv;
-                        phi = fma(wxz, sy, phi);
-                        if constexpr (FIELD) {
-                            ey = fma(wxz, sty, ey);
-                            ex = fma(ddx * wxz, sy, ex);
-                            ez = fma(wx * tzw, sy, ez);
+                            sy = fma(wyw[u0 + u], hv[u], sy);
+                            if constexpr (FIELD) sty = fma(tyw[u0 + u], hv[u], sty);
                         }
                     }
+                    sp = fma(wx, sy, sp);
+                    if constexpr (FIELD) {
+                        spx = fma((dx0 - (T)dx * h) * wx, sy, spx);
+                        spy = fma(wx, sty, spy);
+                    }
+                }
+                phi = fma(wzv, sp, phi);
+                if constexpr (FIELD) {
+                    ex = fma(wzv, spx, ex);
+                    ey = fma(wzv, spy, ey);
+                    ez = fma(tzw, sp, ez);
                 }
             }
+
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
         }
