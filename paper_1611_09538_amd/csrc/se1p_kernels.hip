@@ -1277,7 +1277,6 @@ __device__ __forceinline__ void gather_body(
         }
 
         // Planes stream straight from global memory into LDS (16-byte
-
         // global_load_lds chunks, 64 per instruction), one plane ahead of
         // the plane being read.
         auto stage = [&](int ip, T* buf) {
