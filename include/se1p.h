@@ -142,10 +142,13 @@ typedef struct se1p_plan_info {
     long long n_max;
     size_t workspace_bytes;
     int    gather_block[3];  /* cells per gather block (x, y, z) */
-    int    gather_chunks;    /* 64-particle chunk slots per gather block */
+    int    gather_chunks;    /* waves (one chunk each) per gather unit */
     int    spread_cz;        /* z cells per gridding chunk */
     int    spread_kp;        /* partial grids written by gridding */
     long long bin_cells[2];  /* cells of the lex and block orders of binning */
+    int    gather_pair;      /* 1: a gather unit is two y-adjacent blocks (32
+                                particles of each per chunk), 0: one block
+                                (64 particles per chunk) */
 } se1p_plan_info;
 
 typedef struct se1p_plan se1p_plan;

@@ -187,11 +187,15 @@ int build_batch(se1p_batch& b) {
             lds[kQCols] = std::max(lds[kQCols], 2 * (size_t)ncl * (sd.n1 + 1) * cs);
         }
         lds[kQRowInv] = lds[kQRowFwd];
-        const long long nblk = (long long)bg.nbx * bg.nby * bg.nbz;
+        // gather units: blocks, or pairs of y-adjacent blocks
+        const long long nunit = (long long)bg.nbx * bg.nby * bg.nbz / (1 + bg.pair);
         // a chunk spans about 64 / (rho * BX * BY) z cells of its block
-        const double span = std::min((double)bg.BZ, 64.0 / std::max(rho * bg.BX * bg.BY, 1e-12));
+        // (a pair's chunk 32 / ... plus the drift between its two runs)
+        const double layer = std::max(rho * bg.BX * bg.BY, 1e-12);
+        const double span = std::min((double)bg.BZ, bg.pair ? 32.0 / layer + 0.9 * std::sqrt(rho * bg.cpb) / layer
+                                                            : 64.0 / layer);
         const double cg = (span + P - 1.0) * P * P;
-        for (long long k = 0; k < nblk * bg.CH; ++k)
+        for (long long k = 0; k < nunit * bg.CH; ++k)
             it[kQGather].push_back({cg, Item{s, (int)k, 0, 0}});
         const int Ux = bg.BX + P - 1;
         lds[kQGather] = std::max(lds[kQGather], 2 * (size_t)Ux * bg.ldy * es);

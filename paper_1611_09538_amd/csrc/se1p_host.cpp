@@ -127,14 +127,14 @@ int check_params(const se1p_params& p) {
 // chunk should be full while its z extent stays small.  Expected cost per
 // particle: E[chunks] * union / m, with Poisson counts of mean m = rho *
 // cells, penalised when the launch would not fill the chip.
-double poisson_chunks(double m) {
-    // E[ceil(k / 64)] for k ~ Poisson(m); for large m, m / 64 + 1/2
-    if (m > 400.0) return m / 64.0 + 0.5;
+double poisson_chunks(double m, int size = 64) {
+    // E[ceil(k / size)] for k ~ Poisson(m); for large m, m / size + 1/2
+    if (m > 400.0) return m / size + 0.5;
     double pk = std::exp(-m), acc = 0.0;
     const int kmax = (int)(m + 12.0 * std::sqrt(m + 1.0) + 80.0);
     for (int k = 0; k <= kmax; ++k) {
         if (k > 0) pk *= m / k;
-        acc += pk * ((k + 63) / 64);
+        acc += pk * ((k + size - 1) / size);
     }
     return acc;
 }
@@ -156,19 +156,49 @@ void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
     // sweeps that many planes plus P - 1.  Cost per particle: planes swept
     // per chunk times chunks over the particles per block, with Poisson
     // counts of mean m = rho * cells, penalised when the launch has fewer
-    // waves than the chip has SIMDs.
+    // waves than the chip has SIMDs.  A gather unit may also take two
+    // y-adjacent blocks at once, 32 particles of each per chunk in lanes
+    // 0-31 and 32-63: a 16- or 32-lane LDS cycle then still reads windows
+    // of one block's cells only, and a chunk spans about half the z cells
+    // (plus the drift between the two blocks' runs), over a footprint
+    // BY cells wider.
     const double ncells = (double)pl.M1 * pl.M2 * pl.g.M3;
     const double rho = (double)std::max<long long>(pl.n_max, 1) / ncells;
     const int P = pl.g.P;
     double best = 1e300;
     const int bymin = std::max(2, 16 / (int)pl.es);   // whole 16-byte chunks
     const int nbank = 128 / (int)pl.es;
-    int bx = 1, by = bymin, bz = 1, ch = 1;
+    int bx = 1, by = bymin, bz = 1, ch = 1, pair = 0;
     const int bys[4] = {2, 4, 8, 16};
     std::vector<int> bzs;
     for (int z = 1; z < pl.g.M3; z *= 2)
         if (pl.g.M3 % z == 0) bzs.push_back(z);
     bzs.push_back(pl.g.M3);
+    // Cost of a block shape, with pr = 1 for units of two y-adjacent blocks
+    // (nby even), chunk k the k-th 32 particles of each from the bottom;
+    // the two runs drift apart in z like a random walk.
+    auto shape_cost = [&](int BX, int BY, int BZ, int pr, int& chs) {
+        const double m = rho * BX * BY * BZ;
+        const int nby = (pl.M2 + BY - 1) / BY;
+        const double nblocks = (double)((pl.M1 + BX - 1) / BX) * nby * (pl.g.M3 / BZ);
+        const double layer = std::max(rho * BX * BY, 1e-12);   // particles per z cell
+        const int per = pr ? 32 : 64;
+        const double chunks = std::max(poisson_chunks(m, per) + (pr ? 0.3 : 0.0), 1e-9);
+        double span = per / layer;
+        if (pr) span += 0.9 * std::sqrt(m) / layer;
+        span = std::min((double)BZ, span);
+        const double planes = span + P - 1.0;
+        const double foot = (BX + P - 1.0) * ((1 + pr) * BY + P - 1.0);
+        const double work = chunks * (planes * P * P * 2.0 + planes * foot / 16.0);
+        double cost = (work + 200.0) / std::max((1 + pr) * m, 1e-6);
+        const double waves = nblocks / (1 + pr) * chunks;
+        if (fill && waves < 1024.0) cost *= 1024.0 / std::max(waves, 1.0);
+        chs = std::max(1, (int)std::ceil((m + 3.0 * std::sqrt(m) + 1.0) / per));
+        return cost;
+    };
+    // The shape is chosen for single blocks (it also shapes the chunks of
+    // real-space targets, which follow the block order); the pairing is
+    // then taken for that shape if it costs less.
     for (size_t iz = 0; iz < bzs.size(); ++iz) {
         const int BZ = bzs[iz];
         for (int iy = 0; iy < 4; ++iy) {
@@ -179,27 +209,24 @@ void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
             for (int BX = 1; BX * BY <= nbank; ++BX) {
                 if (mt1 > 0 && ((pl.M1 + BX - 1) / BX) * BX + P > mt1) continue;
                 if (mt2 > 0 && ((pl.M2 + BY - 1) / BY) * BY + P > mt2) continue;
-                const double m = rho * BX * BY * BZ;
-                const double nblocks = (double)((pl.M1 + BX - 1) / BX) *
-                                       ((pl.M2 + BY - 1) / BY) * (pl.g.M3 / BZ);
-                const double chunks = std::max(poisson_chunks(m), 1e-9);
-                const double span = std::min((double)BZ, 64.0 / (rho * BX * BY));
-                const double planes = span + P - 1.0;
-                const double work = chunks * (planes * P * P * 2.0 +
-                                              planes * (BX + P - 1.0) * (BY + P - 1.0) / 16.0);
-                double cost = (work + 200.0) / std::max(m, 1e-6);
-                const double waves = nblocks * chunks;
-                if (fill && waves < 1024.0) cost *= 1024.0 / std::max(waves, 1.0);
+                int chs;
+                const double cost = shape_cost(BX, BY, BZ, 0, chs);
                 if (cost < best) {
-                    best = cost; bx = BX; by = BY; bz = BZ;
-                    ch = std::max(1, (int)std::ceil((m + 3.0 * std::sqrt(m) + 1.0) / 64.0));
+                    best = cost; bx = BX; by = BY; bz = BZ; ch = chs;
                 }
             }
         }
     }
+    if (((pl.M2 + by - 1) / by) % 2 == 0) {
+        int chs;
+        if (shape_cost(bx, by, bz, 1, chs) < best) {
+            pair = 1;
+            ch = chs;
+        }
+    }
     BinGeo& b = pl.bg;
-    b.BX = bx; b.BY = by; b.BZ = bz; b.CH = ch;
-    const int Uy = by + P - 1;
+    b.BX = bx; b.BY = by; b.BZ = bz; b.CH = ch; b.pair = pair;
+    const int Uy = (1 + pair) * by + P - 1;
     b.ldy = Uy + (((by - Uy) % nbank) + nbank) % nbank;   // >= Uy, == BY (mod nb)
     b.nbx = (pl.M1 + bx - 1) / bx;
     b.nby = (pl.M2 + by - 1) / by;
@@ -447,7 +474,7 @@ size_t se1p::layout_scratch(const se1p_plan& pl, long long n, PlanScratch& w,
         w.Hper = w.Htp = nullptr;
     }
     c.take(&w.G, (size_t)pl.slab_elems * cs);
-    c.take(&w.Ht, (size_t)(pl.pstride + 64) * pl.es);   // rows are read in halves
+    c.take(&w.Ht, (size_t)(pl.pstride + 64) * pl.es);   // staging reads past the last row
     if (!pl.periodic3 && ik) {
         c.take(&w.Gk, 3 * (size_t)pl.slab_elems * cs);
         c.take(&w.Htk, 3 * (size_t)(pl.pstride + 64) * pl.es);
@@ -913,6 +940,7 @@ int se1p_plan_get_info(const se1p_plan* pl, se1p_plan_info* info) {
     info->spread_kp = pl->KP;
     info->bin_cells[0] = pl->bg.ncell_lex;
     info->bin_cells[1] = pl->bg.ncell_blk;
+    info->gather_pair = pl->bg.pair;
     return SE1P_OK;
 }
 

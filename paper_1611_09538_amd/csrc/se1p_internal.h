@@ -55,11 +55,15 @@ struct Geo {
 //   block order blocks of BZ x BX x BY cells, lexicographic inside  -- gather
 struct BinGeo {
     int BX, BY, BZ;
-    int CH;               // gather waves per block (chunks of 64 particles)
-    int ldy;              // gather LDS row pitch: >= BY + P - 1 and
-                          // == BY (mod nb), nb = 128 / word size; with
+    int CH;               // gather waves per gather unit (one chunk each)
+    int pair;             // 1: a gather unit is two y-adjacent blocks, the
+                          // even one and the next (nby even), 32 lanes
+                          // each; 0: one block, 64 lanes
+    int ldy;              // gather LDS row pitch: >= (1 + pair) BY + P - 1
+                          // and == BY (mod nb), nb = 128 / word size; with
                           // BX * BY <= nb the window origins of distinct
-                          // cells then fall in distinct LDS banks
+                          // cells of one block then fall in distinct LDS
+                          // banks
     int nbx, nby, nbz;
     int cpb;              // cells per block
     long long ncell_lex;  // M3 * M1 * M2

@@ -1185,14 +1185,26 @@ __device__ __forceinline__ void gather_body(
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     constexpr int HP = P / 2;         // rows are read from LDS in two halves
-    const int b = bid / CH;
-    const int slot = bid - b * CH;
+    const int unit = bid / CH;
+    const int slot = bid - unit * CH;
+    // A unit is one block, or (pair) the even block 2 unit and the next one,
+    // its y neighbour in the same row of blocks (nby is even).  The odd
+    // block holds its cells with z reversed.
+    const int b = bg.pair ? 2 * unit : unit;
     int bzk, bxk, byk;
     block_coords(b, bg, bzk, bxk, byk);
-    const int s = cstart[(long long)b * bg.cpb];
-    const int e = cstart[(long long)(b + 1) * bg.cpb];
+    int ylo = byk;
+    if (bg.pair) {
+        int bz2, bx2, by2;
+        block_coords(b + 1, bg, bz2, bx2, by2);
+        ylo = min(byk, by2);
+    }
+    const int sA = cstart[(long long)b * bg.cpb];
+    const int eA = cstart[(long long)(b + 1) * bg.cpb];
+    const int eB = bg.pair ? cstart[(long long)(b + 2) * bg.cpb] : eA;
+    const int nA = eA - sA, nB = eB - eA;
     const int X0u = bxk * bg.BX + 1;  // array index of the footprint start
-    const int Y0u = byk * bg.BY + 1;
+    const int Y0u = ylo * bg.BY + 1;
     const int Ux = bg.BX + P - 1;
     const int ldy = bg.ldy;           // LDS row pitch (see BinGeo)
     const int zl0 = bzk * bg.BZ - P / 2 + 1;  // z index of the union start
@@ -1208,13 +1220,32 @@ __device__ __forceinline__ void gather_body(
     const int rr0 = lane * per16 / ldy, cc0 = lane * per16 - rr0 * ldy;
     const int rstep = 64 * per16 / ldy, cstep = 64 * per16 - rstep * ldy;
 
-    for (int c0 = s + 64 * slot; c0 < e; c0 += 64 * CH) {
-        const int p = c0 + lane;
-        const bool act = p < e;
-        const int pp = act ? p : e - 1;
+    // chunk k: particles [64 k, 64 k + 64) of the block, or (pair) the k-th
+    // 32 from the bottom of each block in lanes 0-31 and 32-63, so that a
+    // 16- or 32-lane LDS cycle reads windows of one block's cells only
+    const int nchunk = bg.pair ? max((nA + 31) / 32, (nB + 31) / 32) : (nA + 63) / 64;
+    const int safe = nA > 0 ? sA : eA;   // a particle of the unit (when nchunk > 0)
+    for (int k = slot; k < nchunk; k += CH) {
+        int p;
+        bool act;
+        if (bg.pair) {
+            const int l = lane & 31;
+            if (lane < 32) {
+                act = 32 * k + l < nA;
+                p = sA + 32 * k + l;
+            } else {
+                const int j = nB - 32 * (k + 1) + l;
+                act = j >= 0;
+                p = eA + j;
+            }
+        } else {
+            act = 64 * k + lane < nA;
+            p = sA + 64 * k + lane;
+        }
+        const int pp = act ? p : safe;
         const T tx = ptx[pp], ty = pty[pp], tz = ptz[pp];
         const int ox = pcx[pp] - bxk * bg.BX;
-        const int oy = pcy[pp] - byk * bg.BY;
+        const int oy = pcy[pp] - ylo * bg.BY;
         const int oz = pcz[pp] - bzk * bg.BZ;
         int ozmin = act ? oz : 1 << 20, ozmax = act ? oz : -(1 << 20);
 #pragma unroll
@@ -2367,7 +2398,7 @@ int launch_kspace_ik(const T* Hin, int KP, long long pstride, const Geo& g,
 template <typename T, int P>
 static int gather_phi_p(const T* Ht, const DevParticles<T>& blk, const Geo& g,
                         const BinGeo& bg, T scale, T* out, int ostride, hipStream_t s) {
-    const unsigned nb = (unsigned)(bg.nbx * bg.nby * bg.nbz) * bg.CH;
+    const unsigned nb = (unsigned)(bg.nbx * bg.nby * bg.nbz / (1 + bg.pair)) * bg.CH;
     const size_t lds = 2 * (size_t)(bg.BX + P - 1) * bg.ldy * sizeof(T);
     hipLaunchKernelGGL((gather_phi_kernel<T, P>), dim3(nb), dim3(64), lds, s, Ht,
                        blk.tx, blk.ty, blk.tz, blk.cx, blk.cy, blk.cz, blk.perm,
@@ -2392,9 +2423,8 @@ template <typename T, int P>
 static int gather_p(const T* Ht, const DevParticles<T>& blk, const Geo& g,
                     const BinGeo& bg, T scale, T* phi_out, T* E_out,
                     hipStream_t s) {
-    const unsigned nb = (unsigned)(bg.nbx * bg.nby * bg.nbz) * bg.CH;
-    const int Ux = bg.BX + P - 1, Uy = bg.BY + P - 1;
-    (void)Uy;
+    const unsigned nb = (unsigned)(bg.nbx * bg.nby * bg.nbz / (1 + bg.pair)) * bg.CH;
+    const int Ux = bg.BX + P - 1;
     const size_t lds = 2 * (size_t)Ux * bg.ldy * sizeof(T);
     hipLaunchKernelGGL((gather_kernel<T, P>), dim3(nb), dim3(64), lds, s, Ht,
                        blk.tx, blk.ty, blk.tz, blk.cx, blk.cy, blk.cz, blk.perm,

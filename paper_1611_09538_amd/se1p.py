@@ -90,6 +90,7 @@ class PlanInfo(ctypes.Structure):
         ("spread_cz", ctypes.c_int),
         ("spread_kp", ctypes.c_int),
         ("bin_cells", ctypes.c_longlong * 2),
+        ("gather_pair", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -100,7 +101,8 @@ class PlanInfo(ctypes.Structure):
                 "n_max": self.n_max, "workspace_bytes": self.workspace_bytes,
                 "gather_block": tuple(self.gather_block),
                 "gather_chunks": self.gather_chunks, "spread_cz": self.spread_cz,
-                "spread_kp": self.spread_kp, "bin_cells": tuple(self.bin_cells)}
+                "spread_kp": self.spread_kp, "bin_cells": tuple(self.bin_cells),
+                "gather_pair": self.gather_pair}
 
 
 class CostModel(ctypes.Structure):
