@@ -14,8 +14,9 @@
 //              (eq. scale_1p with G of eq. G_kappa_k) -> inverse column FFT,
 //              inverse row FFTs, inverse z FFT; Stockham FFTs in LDS
 //   gather     step 6 (eq. se1p_complete_discretized) and its analytic
-//              gradient (eq. force_se1p): one lane per particle, the grid
-//              planes a chunk's supports touch staged in LDS
+//              gradient (eq. force_se1p): one lane per particle, chunks of
+//              one block or of two y-adjacent blocks, the grid planes a
+//              chunk's supports touch staged in LDS
 //   realspace  eq. ewald1p_real / eq. force_real over the cell list
 //   combine    totals, self term (eq. ewald1p_self), energy 1/2 sum q phi
 //
@@ -1162,16 +1163,17 @@ __global__ __launch_bounds__(256) void rowinv_kernel(
 // ------------------------------------------------------------------------
 // gather (step 6) and its gradient
 // ------------------------------------------------------------------------
-// Lanes are particles: work unit bid takes chunks of 64 consecutive
-// particles of one block of BX x BY x BZ cells (block bid / CH, chunk slot
-// bid % CH; further chunks of a block are strided by CH).  The grid planes
-// the chunk's supports touch are staged one at a time in LDS (global_load_lds
-// of the block's (BX + P - 1) x (BY + P - 1) footprint, the next plane in
-// flight while the current one is read); each lane then reads its own P x P
-// window of the plane from LDS.  y weights live in registers, x weights
-// follow the Gaussian-gridding recurrence w(u+1) = w(u) r(u),
-// r(u+1) = r(u) exp(-2 alpha h^2) in FP64 (FP32 evaluates exp directly),
-// z weights are one exp per plane.
+// Lanes are particles: work unit bid / CH takes chunks of one block of
+// BX x BY x BZ cells (64 consecutive particles per chunk), or of two
+// y-adjacent blocks (32 of each per chunk); chunk slot bid % CH, further
+// chunks strided by CH.  The grid planes the chunk's supports touch are
+// staged one at a time in LDS (global_load_lds of the unit's footprint, the
+// next plane in flight while the current one is read); each lane then reads
+// its own P x P window of the plane from LDS.  FP64: the y weights of the
+// window live in registers and x weights follow the Gaussian-gridding
+// recurrence w(u+1) = w(u) r(u), r(u+1) = r(u) exp(-2 alpha h^2); FP32
+// evaluates every x and y weight once from its offset; z weights are one
+// exp per plane.
 
 template <typename T, int P, bool FIELD = true>
 __device__ __forceinline__ void gather_body(
