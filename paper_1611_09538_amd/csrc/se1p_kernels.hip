@@ -76,6 +76,21 @@ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) {
     cplx<T> r; r.x = a.x * s; r.y = a.y * s; return r;
 }
 
+// Division by a divisor d >= 1 fixed for a loop: m = floor((2^32 - 1) / d)
+// + 1 makes q = umulhi(a, m) exact for a d < 2^32 (the error a (m d - 2^32)
+// / (d 2^32) stays below 1/d); d = 1 takes q = a.  The FFT index maps divide
+// by pass lengths known only at run time, and the compiler's generic
+// division costs about 15 instructions each.
+struct UDiv {
+    unsigned m;
+    int d;
+    __device__ __forceinline__ explicit UDiv(int dd)
+        : m(dd > 1 ? 0xFFFFFFFFu / (unsigned)dd + 1u : 0u), d(dd) {}
+    __device__ __forceinline__ int operator()(int a) const {
+        return d > 1 ? (int)__umulhi((unsigned)a, m) : a;
+    }
+};
+
 // ------------------------------------------------------------------------
 // Stockham FFT in LDS, block-cooperative, mixed radix 2/3/4/5.
 // 'batch' transforms of length n start at a + b*stride; b is scratch of the
@@ -94,13 +109,15 @@ __device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int batch, int stride,
         const int nR = n / R;
         const int tstep = n / (Ns * R);
         const int total = batch * nR;
+        const UDiv divR(nR), divN(Ns);
         for (int t = threadIdx.x; t < total; t += blockDim.x) {
-            const int bi = t / nR;
+            const int bi = divR(t);
             const int j = t - bi * nR;
             const cplx<T>* src = a + (long)bi * stride;
             cplx<T>* dst = b + (long)bi * stride;
-            const int k = j % Ns;
-            const int base = (j / Ns) * Ns * R + k;
+            const int jq = divN(j);
+            const int k = j - jq * Ns;
+            const int base = jq * Ns * R + k;
             const int tb = k * tstep;
             if (R == 4) {
                 cplx<T> v0 = src[j], v1 = src[j + nR], v2 = src[j + 2 * nR], v3 = src[j + 3 * nR];
@@ -979,6 +996,7 @@ __device__ __forceinline__ void rowfwd_body(
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SlabDesc& sd = slabs[slab];   // by reference: no private copy
     const int n2 = sd.n2;
+    const UDiv divn2(n2);
     const int x0 = rb * nrb;
     if (x0 >= g.Mt1) return;
     const int nr = min(nrb, g.Mt1 - x0);
@@ -986,7 +1004,7 @@ __device__ __forceinline__ void rowfwd_body(
     cplx<T>* B = A + nrb * n2;
     const cplx<T>* src = Fz + (long long)slab * g.ncol;
     for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
-        const int r = idx / n2, j = idx - r * n2;
+        const int r = divn2(idx), j = idx - r * n2;
         cplx<T> v;
         v.x = v.y = (T)0;
         if (j < g.Mt2) v = src[(long long)(x0 + r) * g.Mt2 + j];
@@ -996,7 +1014,7 @@ __device__ __forceinline__ void rowfwd_body(
     cplx<T>* X = fft_lds<T>(A, B, nr, n2, sd.d2, tw + sd.d2.twoff, -1);
     cplx<T>* dst = G + sd.off;
     for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
-        const int r = idx / n2, j = idx - r * n2;
+        const int r = divn2(idx), j = idx - r * n2;
         dst[(long long)(x0 + r) * n2 + j] = X[r * n2 + j];
     }
 }
@@ -1011,22 +1029,34 @@ __global__ __launch_bounds__(256) void rowfwd_kernel(
 
 // Scaling factor (eq. scale_1p with G of eq. G_kappa_k), all constants and
 // transform normalisations included.  Slab 0 uses the FP64 host table S0.
+// Per-slab constants of the scaling: wave numbers k1 = c1 f1, k2 = c2 f2
+// (f the signed frequency index), k3^2, and the Gaussian factor's
+// coefficient (1 - eta) / (4 xi^2), so that no element divides by them.
+struct SlabK {
+    double c1, c2, k3s, ce;
+    __device__ __forceinline__ SlabK(const SlabDesc& sd, const Geo& g) {
+        const double twopi = 6.283185307179586476925286766559;
+        c1 = twopi / (sd.n1 * g.h);
+        c2 = twopi / (sd.n2 * g.h);
+        const double k3 = twopi * sd.n3 / g.L3;
+        k3s = k3 * k3;
+        ce = (1.0 - g.eta) / (4.0 * g.xi * g.xi);
+    }
+};
+
 template <typename T>
-__device__ __forceinline__ T slab_scale(const SlabDesc& sd, int kx, int ky,
-                                        const Geo& g,
-                                        const T* __restrict__ S0) {
+__device__ __forceinline__ T slab_scale(const SlabDesc& sd, const SlabK& kc, int kx,
+                                        int ky, const T* __restrict__ S0) {
     if (sd.n3 == 0) return S0[(long long)kx * sd.n2 + ky];
-    const double twopi = 6.283185307179586476925286766559;
     const int fx = (kx <= sd.n1 / 2) ? kx : kx - sd.n1;
     const int fy = (ky <= sd.n2 / 2) ? ky : ky - sd.n2;
-    const double k1 = twopi * fx / (sd.n1 * g.h);
-    const double k2 = twopi * fy / (sd.n2 * g.h);
-    const double k3 = twopi * sd.n3 / g.L3;
-    const double k2s = k1 * k1 + k2 * k2 + k3 * k3;
+    const double k1 = kc.c1 * fx;
+    const double k2 = kc.c2 * fy;
+    const double k2s = k1 * k1 + k2 * k2 + kc.k3s;
     if constexpr (sizeof(T) == 8) {
-        return (T)(sd.pref * exp(-(1.0 - g.eta) * k2s / (4.0 * g.xi * g.xi)) / k2s);
+        return (T)(sd.pref * exp(-kc.ce * k2s) / k2s);
     } else {
-        const float e = (float)(-(1.0 - g.eta) * k2s / (4.0 * g.xi * g.xi));
+        const float e = (float)(-kc.ce * k2s);
         return (float)sd.pref * __expf(e) / (float)k2s;
     }
 }
@@ -1069,11 +1099,12 @@ __device__ __forceinline__ void cols_body(
     if (k0 >= n2) return;
     const int nc = min(ncb, n2 - k0);
     const int stride = n1 + 1;
+    const UDiv divc(ncb);
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* B = A + ncb * stride;
     cplx<T>* base = G + sd.off;
     for (int idx = threadIdx.x; idx < n1 * ncb; idx += blockDim.x) {
-        const int x = idx / ncb, c = idx - x * ncb;
+        const int x = divc(idx), c = idx - x * ncb;
         cplx<T> v;
         v.x = v.y = (T)0;
         if (x < g.Mt1 && c < nc) v = base[(long long)x * n2 + k0 + c];
@@ -1083,9 +1114,11 @@ __device__ __forceinline__ void cols_body(
     cplx<T>* X = fft_lds<T>(A, B, ncb, stride, sd.d1,
                             tw + sd.d1.twoff, -1);
     cplx<T>* Y = (X == A) ? B : A;
+    const SlabK kc(sd, g);
+    const UDiv div1(n1);
     for (int idx = threadIdx.x; idx < n1 * ncb; idx += blockDim.x) {
-        const int c = idx / n1, kx = idx - c * n1;
-        const T s = (c < nc) ? slab_scale<T>(sd, kx, k0 + c, g, S0) : (T)0;
+        const int c = div1(idx), kx = idx - c * n1;
+        const T s = (c < nc) ? slab_scale<T>(sd, kc, kx, k0 + c, S0) : (T)0;
         cplx<T> v = cscale<T>(X[c * stride + kx], s);
         if (dir >= 0) {
             // (-i k)(a + i b) = k b - i k a
@@ -1100,7 +1133,7 @@ __device__ __forceinline__ void cols_body(
     cplx<T>* Z = fft_lds<T>(X, Y, ncb, stride, sd.d1,
                             tw + sd.d1.twoff, +1);
     for (int idx = threadIdx.x; idx < g.Mt1 * ncb; idx += blockDim.x) {
-        const int x = idx / ncb, c = idx - x * ncb;
+        const int x = divc(idx), c = idx - x * ncb;
         if (c < nc) base[(long long)x * n2 + k0 + c] = Z[c * stride + x];
     }
 }
@@ -1133,6 +1166,7 @@ __device__ __forceinline__ void rowinv_body(
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SlabDesc& sd = slabs[slab];   // by reference: no private copy
     const int n2 = sd.n2;
+    const UDiv divn2(n2);
     const int x0 = rb * nrb;
     if (x0 >= g.Mt1) return;
     const int nr = min(nrb, g.Mt1 - x0);
@@ -1140,14 +1174,15 @@ __device__ __forceinline__ void rowinv_body(
     cplx<T>* B = A + nrb * n2;
     const cplx<T>* src = G + sd.off;
     for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
-        const int r = idx / n2, j = idx - r * n2;
+        const int r = divn2(idx), j = idx - r * n2;
         A[r * n2 + j] = src[(long long)(x0 + r) * n2 + j];
     }
     __syncthreads();
     cplx<T>* X = fft_lds<T>(A, B, nr, n2, sd.d2, tw + sd.d2.twoff, +1);
     cplx<T>* dst = Fz + (long long)slab * g.ncol;
+    const UDiv divm(g.Mt2);
     for (int idx = threadIdx.x; idx < nr * g.Mt2; idx += blockDim.x) {
-        const int r = idx / g.Mt2, j = idx - r * g.Mt2;
+        const int r = divm(idx), j = idx - r * g.Mt2;
         dst[(long long)(x0 + r) * g.Mt2 + j] = X[r * n2 + j];
     }
 }
