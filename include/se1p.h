@@ -85,6 +85,11 @@ extern "C" {
                                   -i k times the scaled spectrum, three more
                                   inverse transforms and potential-only
                                   gathers; SE1P plans only */
+#define SE1P_FORCE       256u  /* efield receives the force q_m E_m on every
+                                  particle (the field of eq. force_se1p and
+                                  eq. force_real times the particle's charge)
+                                  instead of E_m; the totals kernel forms
+                                  the product */
 
 /*
  * Method parameters (Algorithm 1 input, section 4.3 recipe).

@@ -8,7 +8,8 @@ gridding.  Hence, with U = 1/2 q^T A q (section 3.5 read with the usual 1/2):
 
   dU/dq_m = phi_m
   dU/dx_m = -q_m E_m            (E = -grad phi, the gather gradient of
-                                 eq. force_se1p for the k-space part)
+                                 eq. force_se1p for the k-space part; the
+                                 library returns q_m E_m itself, SE1P_FORCE)
 
 and for a loss L(phi) with upstream gradient g = dL/dphi:
 
@@ -31,17 +32,18 @@ class SE1PEnergy(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, q, plan):
-        phi, E, U = plan.eval(x, q, flags=se1p.ALL)
-        ctx.save_for_backward(q, phi, E)
+        # the library writes the force q_m E_m (SE1P_FORCE) next to phi
+        phi, F, U = plan.eval(x, q, flags=se1p.ALL | se1p.FORCE)
+        ctx.save_for_backward(phi, F)
         return U.reshape(())
 
     @staticmethod
     def backward(ctx, gU):
-        q, phi, E = ctx.saved_tensors
+        phi, F = ctx.saved_tensors
         g = gU.to(phi.dtype)
         grad_x = grad_q = None
         if ctx.needs_input_grad[0]:
-            grad_x = -g * q[:, None] * E
+            grad_x = -g * F
         if ctx.needs_input_grad[1]:
             grad_q = g * phi
         return grad_x, grad_q, None

@@ -404,7 +404,7 @@ int build_batch(se1p_batch& b) {
 
 int run_batch(se1p_batch& b, hipStream_t s, const void* x, const void* q,
               void* phi, void* E, double* energy, unsigned flags) {
-    const unsigned comp = flags & SE1P_ALL;
+    const unsigned comp = flags & (SE1P_ALL | SE1P_FORCE);
     if (b.prec == SE1P_FP64)
         return launch_batch<double>(b.a64, (const double*)x, (const double*)q,
                                     (double*)phi, (double*)E, energy, comp, s);
@@ -595,7 +595,7 @@ int se1p_batch_destroy(se1p_batch* b) {
 int se1p_batch_eval(se1p_batch* b, const void* x, const void* q, void* phi,
                     void* efield, double* energy, unsigned flags) {
     if (!b || !x || !q) return SE1P_ERR_ARG;
-    if (flags & ~(SE1P_ALL | SE1P_BATCH_EAGER)) return SE1P_ERR_ARG;
+    if (flags & ~(SE1P_ALL | SE1P_BATCH_EAGER | SE1P_FORCE)) return SE1P_ERR_ARG;
     if ((flags & SE1P_ALL) == 0) return SE1P_ERR_ARG;
     if (hipSetDevice(b->device) != hipSuccess) return SE1P_ERR_HIP;
     if (flags & SE1P_BATCH_EAGER) return run_batch(*b, b->stream, x, q, phi, efield, energy, flags);

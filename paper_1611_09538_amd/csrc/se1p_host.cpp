@@ -638,7 +638,8 @@ int run_eval(se1p_plan& pl, long long N, const void* x, const void* q,
     const double self_c = 2.0 * pl.prm.xi / std::sqrt(kPi);
     const int nb = (int)((N + 255) / 256);
     rc = launch_combine<T>(N, (const T*)q, (const T*)pl.w.phiF, (const T*)pl.w.EF,
-                           (const T*)pl.w.phiR, (const T*)pl.w.ER, pl.w.rs_parts, self_c, comp,
+                           (const T*)pl.w.phiR, (const T*)pl.w.ER, pl.w.rs_parts, self_c,
+                           comp | (flags & SE1P_FORCE),
                            (T*)phi, (T*)efield, pl.w.partials, nb, energy,
                            pl.stream);
     if (rc) return rc;
@@ -693,7 +694,7 @@ int set_device(const se1p_plan* pl) {
 int eval_args(const se1p_plan* pl, long long N, const void* x, const void* q,
               unsigned flags) {
     if (!pl || !x || !q) return SE1P_ERR_ARG;
-    if (flags & ~(SE1P_ALL | SE1P_CHECK_INPUT | SE1P_NO_NEUTRAL | SE1P_FIELD_IK))
+    if (flags & ~(SE1P_ALL | SE1P_CHECK_INPUT | SE1P_NO_NEUTRAL | SE1P_FIELD_IK | SE1P_FORCE))
         return SE1P_ERR_ARG;
     if ((flags & SE1P_FIELD_IK) && pl->periodic3) return SE1P_ERR_UNSUPPORTED;
     if ((flags & SE1P_ALL) == 0) return SE1P_ERR_ARG;

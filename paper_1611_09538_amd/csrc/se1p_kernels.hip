@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "erfcx_poly.h"
+#include "se1p.h"
 #include "se1p_internal.h"
 
 namespace se1p {
@@ -1930,7 +1931,7 @@ __device__ __forceinline__ void combine_body(
                     for (int k = 1; k < nparts; ++k) r += ER[3 * (k * pstr + i) + d];
                     v += r;
                 }
-                E[3 * i + d] = v;
+                E[3 * i + d] = (flags & SE1P_FORCE) ? qi * v : v;
             }
         }
         u = (double)qi * (double)ph;
@@ -2644,7 +2645,7 @@ static int batch_p(const BatchArgs<T>& a, const T* x, const T* q, T* phi,
     hipLaunchKernelGGL(bcombine_kernel<T>, dim3(L[kQComb].grid),
                        dim3(kCombineThreads), 0, s, a.sys, L[kQComb].items,
                        L[kQComb].qb, a.qctr + 8 * kQCtrStride * kQComb, q, a.phiF, a.EF,
-                       a.phiR, a.ER, flags & 7u, phi, E, a.partials);
+                       a.phiR, a.ER, flags & (7u | SE1P_FORCE), phi, E, a.partials);
     SE1P_CHECK_LAUNCH();
     if (energy) {
         hipLaunchKernelGGL(benergy_kernel<T>, dim3(a.nsys), dim3(256), 0, s,

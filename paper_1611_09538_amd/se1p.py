@@ -39,6 +39,7 @@ ALL = 7
 CHECK_INPUT = 16
 NO_NEUTRAL = 32
 FIELD_IK = 128
+FORCE = 256
 BATCH_EAGER = 64
 
 

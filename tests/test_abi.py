@@ -94,3 +94,17 @@ def test_plan_create_rejects_bad_sizes():
 
 def test_eval_rejects_null_plan():
     assert se1p._lib().se1p_eval(None, 10, None, None, None, None, None, 7) == se1p.ERR_ARG
+
+
+def test_flag_values_match_the_header():
+    # the binding's flag constants are the header's #defines
+    txt = open(os.path.join(ROOT, "include", "se1p.h")).read()
+    defs = dict(re.findall(r"#define SE1P_([A-Z_0-9]+)\s+(\d+)u", txt))
+    for name in ("KSPACE", "REAL", "SELF", "ALL", "CHECK_INPUT", "NO_NEUTRAL",
+                 "FIELD_IK", "FORCE", "BATCH_EAGER"):
+        assert int(defs[name]) == getattr(se1p, name), name
+    # component and option bits do not overlap
+    opts = [se1p.CHECK_INPUT, se1p.NO_NEUTRAL, se1p.FIELD_IK, se1p.FORCE, se1p.BATCH_EAGER]
+    for o in opts:
+        assert o & se1p.ALL == 0 and bin(o).count("1") == 1
+    assert len(set(opts)) == len(opts)
