@@ -114,7 +114,7 @@ int build_batch(se1p_batch& b) {
     const int ns = b.nsys;
     const size_t es = sizeof(T), cs = 2 * sizeof(T);
     const int P = b.P;
-    const int PW = P + 2 * weight_pad((int)es);
+    const int PW = P;                    // x / y weight row (no padding)
     BatchArgs<T>& a = args_of<T>(b);
     a = BatchArgs<T>{};
 

@@ -461,7 +461,7 @@ size_t se1p::layout_scratch(const se1p_plan& pl, long long n, PlanScratch& w,
     c.take(&w.lex_i[4], (pl.bg.ncell_lex + 1) * 4);
     c.take(&w.blk_i[4], (pl.bg.ncell_blk + 1) * 4);
     for (int k = 0; k < 7; ++k) { c.take(&w.lex_f[k], N * pl.es); c.take(&w.blk_f[k], N * pl.es); }
-    const int PW = p.P + 2 * weight_pad((int)pl.es);
+    const int PW = p.P;                  // x / y weight row (no padding)
     c.take(&w.wz, (size_t)N * p.P * pl.es);
     c.take(&w.wxp, (size_t)N * PW * pl.es);
     c.take(&w.wyq, (size_t)N * PW * pl.es);

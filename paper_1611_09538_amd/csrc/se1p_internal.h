@@ -13,11 +13,6 @@ constexpr int kSpreadTile = 8;   // spread tile: 8 x 8 (x, y) pencils, one per l
 // Waves per spread tile, splitting its particles: worth it when a particle
 // brings enough work (P z-points per lane) to pay for the per-plane LDS sum.
 constexpr int spread_waves(int P) { return P >= 20 ? 8 : (P >= 16 ? 4 : 1); }
-constexpr int kPad = 7;          // zero padding on each side of the x/y spread weights
-// Padding of the x/y spread weights for an element size: FP64 keeps the
-// zero padding (plain reads in the gridding loop); FP32 stores P entries and
-// clamps its reads, since there the weight bytes cost more than the select.
-constexpr int weight_pad(int es) { return es == 4 ? 0 : kPad; }
 constexpr int kZfftCols = 32;    // columns per block in the z transforms
 constexpr int kMaxP = 32;
 

@@ -566,16 +566,18 @@ __global__ void bin_gather_kernel(const T* __restrict__ xin,
 // spreading (step 2)
 // ------------------------------------------------------------------------
 // Per particle (lex order): z weights wz[P] (wave-uniform in the spread
-// kernel) and x weights wxp[PW], q * y weights wyq[PW], PW = P + 2 pad with
-// pad = weight_pad(sizeof(T)) zeros on each side.
+// kernel), x weights wxp[P] and q * y weights wyq[P]; the gridding loop
+// clamps a lane's index into the row and zeroes the weight outside the
+// support (rows padded with zeros instead, 7 on each side, were slower in
+// FP64 as well as FP32: more weight bytes through the caches).
 //
 // FP64: one weight per thread, each from its own exponential, so that the
-// stores are coalesced: elements [0, N PW) are wxp, [N PW, 2 N PW) wyq and
-// [2 N PW, 2 N PW + N P) wz.  (One row per thread with the Gaussian
-// recurrence was slower here: 3N threads of long dependent chains.)
+// stores are coalesced: elements [0, N P) are wxp, [N P, 2 N P) wyq and
+// [2 N P, 3 N P) wz.  (One row per thread with the Gaussian recurrence was
+// slower here: 3N threads of long dependent chains.)
 template <typename T, int P>
 constexpr long long spread_weight_count(long long N) {
-    return N * (2 * (P + 2 * weight_pad((int)sizeof(T))) + P);
+    return 3 * N * P;
 }
 
 template <typename T, int P>
@@ -586,23 +588,18 @@ __device__ __forceinline__ void spread_weight_elem(const DevParticles<T>& lx,
                                                    T* __restrict__ wxp,
                                                    T* __restrict__ wyq) {
     static_assert(sizeof(T) == 8, "FP32 weights are written one row per thread");
-    constexpr int pad = weight_pad((int)sizeof(T));
-    constexpr int PW = P + 2 * pad;
     const T h = (T)g.h, a = (T)g.alpha;
-    const long long nxy = N * PW;
+    const long long nxy = N * P;
     if (i < 2 * nxy) {
         const bool isy = i >= nxy;
         const long long j = isy ? i - nxy : i;
-        const long long p = j / PW;
+        const long long p = j / P;
         // distance to grid point cx + 1 + u - P/2 (array index) in units of h
-        const int u = (int)(j - p * PW) - pad;
-        T w = 0;
-        if (u >= 0 && u < P) {
-            const T t = isy ? lx.ty[p] : lx.tx[p];
-            const T d = (t - (T)(1 + u - P / 2)) * h;
-            w = dexp<T>(-a * d * d);
-            if (isy) w = lx.q[p] * w;
-        }
+        const int u = (int)(j - p * P);
+        const T t = isy ? lx.ty[p] : lx.tx[p];
+        const T d = (t - (T)(1 + u - P / 2)) * h;
+        T w = dexp<T>(-a * d * d);
+        if (isy) w = lx.q[p] * w;
         (isy ? wyq : wxp)[j] = w;
     } else {
         const long long j = i - 2 * nxy;
@@ -623,7 +620,6 @@ __device__ __forceinline__ void spread_weight_row(const DevParticles<float>& lx,
                                                   float* __restrict__ wz,
                                                   float* __restrict__ wxp,
                                                   float* __restrict__ wyq) {
-    static_assert(weight_pad(4) == 0, "FP32 weight rows carry no padding");
     // offset in the cell in units of h; window point u is grid index
     // c + 1 + u - P/2 (c the particle's cell)
     const float t = axis == 0 ? lx.tx[p] : (axis == 1 ? lx.ty[p] : lx.tz[p]);
@@ -665,9 +661,7 @@ __device__ __forceinline__ void spread_weight_thread(const DevParticles<T>& lx,
 template <typename T, int P>
 __device__ __forceinline__ long long spread_weight_particle(long long N, long long i) {
     if constexpr (sizeof(T) == 8) {
-        constexpr int PW = P + 2 * weight_pad(8);
-        const long long nxy = N * PW;
-        return i < 2 * nxy ? (i % nxy) / PW : (i - 2 * nxy) / P;
+        return (i % (N * P)) / P;
     } else {
         return i % N;
     }
@@ -699,8 +693,6 @@ __device__ __forceinline__ void spread_body(
     const int* __restrict__ cstart, T* __restrict__ Hpart,
     long long pstride, const Geo& g, int CZ, int KP, int tbx, int tby,
     int jc) {
-    constexpr int pad = weight_pad((int)sizeof(T));
-    constexpr int PW = P + 2 * pad;
     constexpr int W = spread_waves(P);
     __shared__ T red[W > 1 ? W : 1][64];
     const int lane = threadIdx.x & 63;
@@ -792,15 +784,10 @@ __device__ __forceinline__ void spread_body(
                 auto coef = [&](int pp, int cxp, int cyp) -> T {
                     const int ux = lx - (cxp + 1);
                     const int uy = ly - (cyp + 1);
-                    if constexpr (pad > 0) {
-                        return wxp[(long long)pp * PW + ux + pad] *
-                               wyq[(long long)pp * PW + uy + pad];
-                    } else {
-                        const T wx = wxp[(long long)pp * PW + min(max(ux, 0), P - 1)];
-                        const T wy = wyq[(long long)pp * PW + min(max(uy, 0), P - 1)];
-                        return ((unsigned)ux < (unsigned)P && (unsigned)uy < (unsigned)P)
-                                   ? wx * wy : (T)0;
-                    }
+                    const T wx = wxp[(long long)pp * P + min(max(ux, 0), P - 1)];
+                    const T wy = wyq[(long long)pp * P + min(max(uy, 0), P - 1)];
+                    return ((unsigned)ux < (unsigned)P && (unsigned)uy < (unsigned)P)
+                               ? wx * wy : (T)0;
                 };
                 // FP32: two particles per iteration (their loads in flight
                 // together); FP64: one, since two particles' z weights (2 P
