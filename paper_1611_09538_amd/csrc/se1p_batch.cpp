@@ -189,11 +189,13 @@ int build_batch(se1p_batch& b) {
         lds[kQRowInv] = lds[kQRowFwd];
         // gather units: blocks, or pairs of y-adjacent blocks
         const long long nunit = (long long)bg.nbx * bg.nby * bg.nbz / (1 + bg.pair);
-        // a chunk spans about 64 / (rho * BX * BY) z cells of its block
-        // (a pair's chunk 32 / ... plus the drift between its two runs)
+        // a chunk spans about 64 / (rho * BX * BY) z cells of its block (a
+        // pair's chunk about 32 / ...: plus one (FP64, cut at layers) or
+        // plus the drift of its two runs (FP32))
         const double layer = std::max(rho * bg.BX * bg.BY, 1e-12);
-        const double span = std::min((double)bg.BZ, bg.pair ? 32.0 / layer + 0.9 * std::sqrt(rho * bg.cpb) / layer
-                                                            : 64.0 / layer);
+        const double pspan = es == 8 ? 32.0 / layer + 1.0
+                                     : 32.0 / layer + 0.9 * std::sqrt(rho * bg.cpb) / layer;
+        const double span = std::min((double)bg.BZ, bg.pair ? pspan : 64.0 / layer);
         const double cg = (span + P - 1.0) * P * P;
         for (long long k = 0; k < nunit * bg.CH; ++k)
             it[kQGather].push_back({cg, Item{s, (int)k, 0, 0}});

@@ -175,17 +175,26 @@ void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
         if (pl.g.M3 % z == 0) bzs.push_back(z);
     bzs.push_back(pl.g.M3);
     // Cost of a block shape, with pr = 1 for units of two y-adjacent blocks
-    // (nby even), chunk k the k-th 32 particles of each from the bottom;
-    // the two runs drift apart in z like a random walk.
+    // (nby even).  FP64 cuts a pair's chunks at z-layer boundaries where
+    // neither block has more than 32 particles (on average a layer's worth
+    // short of 32); FP32 takes runs of 32 from each block, which drift
+    // apart in z like a random walk.
+    const bool layer_cut = pl.es == 8;
     auto shape_cost = [&](int BX, int BY, int BZ, int pr, int& chs) {
         const double m = rho * BX * BY * BZ;
         const int nby = (pl.M2 + BY - 1) / BY;
         const double nblocks = (double)((pl.M1 + BX - 1) / BX) * nby * (pl.g.M3 / BZ);
         const double layer = std::max(rho * BX * BY, 1e-12);   // particles per z cell
-        const int per = pr ? 32 : 64;
-        const double chunks = std::max(poisson_chunks(m, per) + (pr ? 0.3 : 0.0), 1e-9);
-        double span = per / layer;
-        if (pr) span += 0.9 * std::sqrt(m) / layer;
+        double per = 64.0, chunks = std::max(poisson_chunks(m, 64), 1e-9), span = per / layer;
+        if (pr && layer_cut) {
+            per = std::max(32.0 - 0.75 * std::min(layer, 32.0), 8.0);
+            chunks = m / per + 0.5;
+            span = per / layer + 1.0;
+        } else if (pr) {
+            per = 32.0;
+            chunks = poisson_chunks(m, 32) + 0.3;
+            span = per / layer + 0.9 * std::sqrt(m) / layer;
+        }
         span = std::min((double)BZ, span);
         const double planes = span + P - 1.0;
         const double foot = (BX + P - 1.0) * ((1 + pr) * BY + P - 1.0);
@@ -217,7 +226,9 @@ void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
             }
         }
     }
-    if (((pl.M2 + by - 1) / by) % 2 == 0) {
+    // (a pair's chunk walk holds the layer counts of 64 kMaxLayerGroups - 1
+    // z cells at most)
+    if (((pl.M2 + by - 1) / by) % 2 == 0 && (!layer_cut || bz < 64 * kMaxLayerGroups)) {
         int chs;
         if (shape_cost(bx, by, bz, 1, chs) < best) {
             pair = 1;

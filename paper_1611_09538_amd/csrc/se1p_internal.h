@@ -14,6 +14,9 @@ constexpr int kSpreadTile = 8;   // spread tile: 8 x 8 (x, y) pencils, one per l
 // brings enough work (P z-points per lane) to pay for the per-plane LDS sum.
 constexpr int spread_waves(int P) { return P >= 20 ? 8 : (P >= 16 ? 4 : 1); }
 constexpr int kZfftCols = 32;    // columns per block in the z transforms
+// Gather units of two blocks walk their z layers 64 per lane group: blocks
+// of up to 64 kMaxLayerGroups - 1 z cells can be paired.
+constexpr int kMaxLayerGroups = 2;
 constexpr int kMaxP = 32;
 
 // One 1D FFT length: radices in pass order and the offset of its twiddle
