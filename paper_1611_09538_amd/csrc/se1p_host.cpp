@@ -202,7 +202,11 @@ void choose_blocks(se1p_plan& pl, bool fill, int mt1, int mt2) {
         double cost = (work + 200.0) / std::max((1 + pr) * m, 1e-6);
         const double waves = nblocks / (1 + pr) * chunks;
         if (fill && waves < 1024.0) cost *= 1024.0 / std::max(waves, 1.0);
-        chs = std::max(1, (int)std::ceil((m + 3.0 * std::sqrt(m) + 1.0) / per));
+        // waves per unit: enough for the chunks of a block 3 sigma above the
+        // mean; FP32 pairs half as many again (shorter waves, 4% faster
+        // at N = 1e6; FP64 pairs 2% slower with them)
+        chs = std::max(1, (int)std::ceil((pr && !layer_cut ? 1.5 : 1.0) *
+                                         (m + 3.0 * std::sqrt(m) + 1.0) / per));
         return cost;
     };
     // The shape is chosen for single blocks (it also shapes the chunks of
