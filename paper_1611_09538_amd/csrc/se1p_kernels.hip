@@ -1583,13 +1583,28 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
 // scaled by 2^k.
 __device__ __forceinline__ double exp_neg(double y) {
     const double k = rint(y * 1.4426950408889634074);
-    double r = fma3(-k, 6.93147180369123816490e-01, y);
-    r = fma3(-k, 1.90821492927058770002e-10, r);
+    double r = fma3(k, -6.93147180369123816490e-01, y);
+    r = fma3(k, -1.90821492927058770002e-10, r);
     double p = kExpC[kExpDeg];
 #pragma unroll
     for (int j = kExpDeg - 1; j >= 0; --j) p = fma3(p, r, kExpC[j]);
     return ldexp(p, (int)k);
 }
+
+// Index of the lowest set bit of m, -1 for m = 0 (v_ffbl_b32 returns all
+// ones for a zero input).
+__device__ __forceinline__ int lowest_bit(unsigned m) {
+    int b;
+    asm("v_ffbl_b32 %0, %1" : "=v"(b) : "v"(m));
+    return b;
+}
+
+// Smallest r^2 the pair terms are evaluated at: at the floor the field
+// factor (about r^-3) stays finite in T, and a lane that adds nothing (charge
+// 0) may sit there.  A pair closer than that is no physical input.
+template <typename T> __device__ __forceinline__ constexpr T rs_r2_floor();
+template <> __device__ __forceinline__ constexpr double rs_r2_floor<double>() { return 1e-150; }
+template <> __device__ __forceinline__ constexpr float rs_r2_floor<float>() { return 1e-24f; }
 
 template <typename T>
 __device__ __forceinline__ void pair_terms(T r2, T xi, T xi2, T c_erf, T qn,
@@ -1616,7 +1631,7 @@ __device__ __forceinline__ void pair_terms<double>(double r2, double xi,
     double t = __builtin_amdgcn_rcp(den);
     t = t * (2.0 - den * t);
     const double cu = 2.0 / (1.0 - kErfcxTmin);
-    const double u = fma(t, cu, -1.0 - kErfcxTmin * cu);
+    const double u = fma3(t, cu, -1.0 - kErfcxTmin * cu);
     double pv = kErfcxC[kErfcxDeg];
 #pragma unroll
     for (int k = kErfcxDeg - 1; k >= 0; --k) pv = fma3(pv, u, kErfcxC[k]);
@@ -1699,20 +1714,33 @@ __device__ __forceinline__ void realspace_body(
             // candidate kq + 4 (b - 16) of the newer one
             // every pass pops one bit per lane, lowest (oldest) first, so
             // the pass count is the largest count of the bits to consume
+            const unsigned jbase = (unsigned)(kq + 64 * old_slot) * sizeof(T);
             int np = __popc(drain ? mask : (mask & 0xFFFFu));
 #pragma unroll
             for (int m = 32; m >= 1; m >>= 1) np = max(np, __shfl_xor(np, m));
             np = __builtin_amdgcn_readfirstlane(np);
             for (int it = 0; it < np; ++it) {
                 const bool has = mask != 0u;
-                const int b = has ? __builtin_ctz(mask) : 0;
-                const int j = (kq + 4 * b + 64 * old_slot) & 127;
+                // lowest set bit; a lane out of bits (b = -1) reads some
+                // staged candidate and adds nothing: its charge is taken
+                // as 0
+                const int b = lowest_bit(mask);
+                // byte offset of entry (kq + 4 b + 64 old_slot) mod 128
+                const unsigned jb = ((unsigned)b * (4u * sizeof(T)) + jbase) &
+                                    (128u * sizeof(T) - 1u);
                 mask &= mask - 1u;
-                const T dx = xt - cx_[j], dy = yt - cy_[j], dz = zt - cz_[j];
+                auto at = [&](const T* a) {
+                    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(a) + jb);
+                };
+                const T dx = xt - at(cx_), dy = yt - at(cy_), dz = zt - at(cz_);
                 const T r2v = dx * dx + dy * dy + dz * dz;
-                const T qv = cq_[j];
-                const T r2 = has ? r2v : (T)1;
-                const T qn = has ? qv : (T)0;
+                const T qv = at(cq_);
+                // the mask pass tests the cut-off only, so the target's own
+                // entry (r2 = 0) has a bit too; it adds nothing either.  The
+                // floor keeps those lanes' reciprocals finite.
+                const bool use = has & (r2v > (T)0);
+                const T r2 = fmax(r2v, rs_r2_floor<T>());
+                const T qn = use ? qv : (T)0;
                 T ec, f;
                 pair_terms<T>(r2, xi, xi2, c_erf, qn, ec, f);
                 phi = fma(qn, ec, phi);
@@ -1732,14 +1760,16 @@ __device__ __forceinline__ void realspace_body(
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 // bitwise, not short-circuit: straight-line compares instead
                 // of a branch per candidate (all j < 64 are in the slot)
-                const bool in = (full | (j < n)) & (r2 <= rc2) & (r2 > (T)0);
-                nmask |= (unsigned int)in << i;
+                const bool in = (full | (j < n)) & (r2 <= rc2);
+                // candidates are tested from the last down, each bit shifted
+                // in from below (one add with carry per candidate)
+                nmask = nmask + nmask + (unsigned int)in;
             };
             if (n == 64) {             // a full batch: straight-line code
 #pragma unroll
-                for (int i = 0; i < 16; ++i) test(i, true);
+                for (int i = 15; i >= 0; --i) test(i, true);
             } else {
-                for (int i = 0; 4 * i < n; ++i) test(i, false);
+                for (int i = (n + 3) / 4 - 1; i >= 0; --i) test(i, false);
             }
             if (!act) nmask = 0u;
             mask |= nmask << 16;
