@@ -92,6 +92,28 @@ struct UDiv {
     }
 };
 
+// Block-cooperative copy of count elements: load(i) reads element i from
+// global memory, store(i, v) puts it into LDS.  Each thread issues kLoadBatch
+// loads before it stores any of them, so their latencies overlap (a loop of
+// one load and one store per element waits for every load in turn).
+constexpr int kLoadBatch = 8;
+template <typename V, typename L, typename S>
+__device__ __forceinline__ void batched_copy(int count, L load, S store) {
+    for (int i0 = threadIdx.x; i0 < count; i0 += kLoadBatch * blockDim.x) {
+        V v[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int i = i0 + u * blockDim.x;
+            if (i < count) v[u] = load(i);
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int i = i0 + u * blockDim.x;
+            if (i < count) store(i, v[u]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------------
 // Stockham FFT in LDS, block-cooperative, mixed radix 2/3/4/5.
 // 'batch' transforms of length n start at a + b*stride; b is scratch of the
@@ -881,17 +903,36 @@ __device__ __forceinline__ void zfft_body(
     cplx<T>* B = A + (CB / 2) * stride;
     const long long ncol = g.ncol;
     const long long c0 = (long long)cbk * CB;
-    for (int idx = threadIdx.x; idx < CB * M3; idx += blockDim.x) {
-        const int z = idx / CB, c = idx - z * CB;
-        const long long col = c0 + c;
-        T v = 0;
-        if (col < ncol) {
-            const T* src = H + (long long)z * ncol + col;
-            for (int k = 0; k < KP; ++k) v += src[k * pstride];
-            v *= in_scale;
+    // kLoadBatch elements per thread at a time, their loads of one partial
+    // grid issued together; the partial grids are added in order k = 0, 1,
+    // ... as for a single element
+    for (int i0 = threadIdx.x; i0 < CB * M3; i0 += kLoadBatch * blockDim.x) {
+        T v[kLoadBatch];
+        long long off[kLoadBatch];
+        bool ok[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = i0 + u * blockDim.x;
+            const int z = idx / CB, c = idx - z * CB;
+            const long long col = c0 + c;
+            ok[u] = idx < CB * M3 && col < ncol;
+            off[u] = (long long)z * ncol + col;
+            v[u] = 0;
         }
-        T* at = reinterpret_cast<T*>(&A[(c >> 1) * stride + z]);
-        at[c & 1] = v;
+        for (int k = 0; k < KP; ++k) {
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u)
+                if (ok[u]) v[u] += H[off[u] + k * pstride];
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = i0 + u * blockDim.x;
+            if (idx < CB * M3) {
+                const int z = idx / CB, c = idx - z * CB;
+                T* at = reinterpret_cast<T*>(&A[(c >> 1) * stride + z]);
+                at[c & 1] = v[u] * in_scale;
+            }
+        }
     }
     __syncthreads();
     cplx<T>* X = fft_lds<T>(A, B, CB / 2, stride, d, tw + d.twoff, -1);
@@ -936,22 +977,29 @@ __device__ __forceinline__ void zifft_body(
     const long long ncol = g.ncol;
     const long long c0 = (long long)cbk * CB;
     const int half = M3 / 2;
-    for (int idx = threadIdx.x; idx < M3 * (CB / 2); idx += blockDim.x) {
-        const int k = idx / (CB / 2), t = idx - k * (CB / 2);
-        const long long ca = c0 + 2 * t, cbb = ca + 1;
-        const int src = (k <= half) ? k : M3 - k;
-        const bool cj = k > half;
-        cplx<T> fa, fb;
-        fa.x = fa.y = fb.x = fb.y = (T)0;
-        if (ca < ncol) fa = Fz[(long long)src * ncol + ca];
-        if (cbb < ncol) fb = Fz[(long long)src * ncol + cbb];
-        if (k == 0 || k == half) { fa.y = (T)0; fb.y = (T)0; }
-        if (cj) { fa.y = -fa.y; fb.y = -fb.y; }
-        cplx<T> z;
-        z.x = fa.x - fb.y;
-        z.y = fa.y + fb.x;
-        A[t * stride + k] = z;
-    }
+    struct Two { cplx<T> a, b; };
+    batched_copy<Two>(
+        M3 * (CB / 2),
+        [&](int idx) {
+            const int k = idx / (CB / 2), t = idx - k * (CB / 2);
+            const long long ca = c0 + 2 * t, cbb = ca + 1;
+            const int src = (k <= half) ? k : M3 - k;
+            Two f;
+            f.a.x = f.a.y = f.b.x = f.b.y = (T)0;
+            if (ca < ncol) f.a = Fz[(long long)src * ncol + ca];
+            if (cbb < ncol) f.b = Fz[(long long)src * ncol + cbb];
+            return f;
+        },
+        [&](int idx, Two f) {
+            const int k = idx / (CB / 2), t = idx - k * (CB / 2);
+            cplx<T> fa = f.a, fb = f.b;
+            if (k == 0 || k == half) { fa.y = (T)0; fb.y = (T)0; }
+            if (k > half) { fa.y = -fa.y; fb.y = -fb.y; }
+            cplx<T> z;
+            z.x = fa.x - fb.y;
+            z.y = fa.y + fb.x;
+            A[t * stride + k] = z;
+        });
     __syncthreads();
     cplx<T>* X = fft_lds<T>(A, B, CB / 2, stride, d, tw + d.twoff, +1);
     for (int idx = threadIdx.x; idx < M3 * CB; idx += blockDim.x) {
@@ -991,13 +1039,16 @@ __device__ __forceinline__ void rowfwd_body(
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* B = A + nrb * n2;
     const cplx<T>* src = Fz + (long long)slab * g.ncol;
-    for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
-        const int r = divn2(idx), j = idx - r * n2;
-        cplx<T> v;
-        v.x = v.y = (T)0;
-        if (j < g.Mt2) v = src[(long long)(x0 + r) * g.Mt2 + j];
-        A[r * n2 + j] = v;
-    }
+    batched_copy<cplx<T>>(
+        nr * n2,
+        [&](int idx) {
+            const int r = divn2(idx), j = idx - r * n2;
+            cplx<T> v;
+            v.x = v.y = (T)0;
+            if (j < g.Mt2) v = src[(long long)(x0 + r) * g.Mt2 + j];
+            return v;
+        },
+        [&](int idx, cplx<T> v) { A[idx] = v; });
     __syncthreads();
     cplx<T>* X = fft_lds<T>(A, B, nr, n2, sd.d2, tw + sd.d2.twoff, -1);
     cplx<T>* dst = G + sd.off;
@@ -1091,13 +1142,19 @@ __device__ __forceinline__ void cols_body(
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* B = A + ncb * stride;
     cplx<T>* base = G + sd.off;
-    for (int idx = threadIdx.x; idx < n1 * ncb; idx += blockDim.x) {
-        const int x = divc(idx), c = idx - x * ncb;
-        cplx<T> v;
-        v.x = v.y = (T)0;
-        if (x < g.Mt1 && c < nc) v = base[(long long)x * n2 + k0 + c];
-        A[c * stride + x] = v;
-    }
+    batched_copy<cplx<T>>(
+        n1 * ncb,
+        [&](int idx) {
+            const int x = divc(idx), c = idx - x * ncb;
+            cplx<T> v;
+            v.x = v.y = (T)0;
+            if (x < g.Mt1 && c < nc) v = base[(long long)x * n2 + k0 + c];
+            return v;
+        },
+        [&](int idx, cplx<T> v) {
+            const int x = divc(idx), c = idx - x * ncb;
+            A[c * stride + x] = v;
+        });
     __syncthreads();
     cplx<T>* X = fft_lds<T>(A, B, ncb, stride, sd.d1,
                             tw + sd.d1.twoff, -1);
@@ -1161,10 +1218,13 @@ __device__ __forceinline__ void rowinv_body(
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* B = A + nrb * n2;
     const cplx<T>* src = G + sd.off;
-    for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
-        const int r = divn2(idx), j = idx - r * n2;
-        A[r * n2 + j] = src[(long long)(x0 + r) * n2 + j];
-    }
+    batched_copy<cplx<T>>(
+        nr * n2,
+        [&](int idx) {
+            const int r = divn2(idx), j = idx - r * n2;
+            return src[(long long)(x0 + r) * n2 + j];
+        },
+        [&](int idx, cplx<T> v) { A[idx] = v; });
     __syncthreads();
     cplx<T>* X = fft_lds<T>(A, B, nr, n2, sd.d2, tw + sd.d2.twoff, +1);
     cplx<T>* dst = Fz + (long long)slab * g.ncol;
