@@ -1974,7 +1974,9 @@ __device__ __forceinline__ void realspace_body(
             aq = lx.q[cand];
         }
         int slot = 0;
+        int nbatch = 0;                // uniform
         while (nA > 0) {
+            ++nbatch;
             __syncthreads();           // the batch before the previous one is done
             cx_[64 * slot + lane] = ax;
             cy_[64 * slot + lane] = ay;
@@ -1994,6 +1996,16 @@ __device__ __forceinline__ void realspace_body(
             az = bz_;
             aq = bq_;
             nA = nB;
+        }
+        // Lanes out of bits read an entry of the newer slot (and multiply it
+        // by a charge of 0).  After a single batch that slot was never
+        // staged: it gets finite values first.
+        if (nbatch == 1) {
+            cx_[64 + lane] = (T)0;
+            cy_[64 + lane] = (T)0;
+            cz_[64 + lane] = (T)0;
+            cq_[64 + lane] = (T)0;
+            __syncthreads();
         }
         // the last batch's carried bits (slot ^ 1 is the last one written)
         pop(slot ^ 1, true);
