@@ -888,9 +888,9 @@ __global__ void reduce_partials_kernel(const T* __restrict__ Hp, int KP,
 // ------------------------------------------------------------------------
 // k-space: z transforms
 // ------------------------------------------------------------------------
-// Forward real FFT along z of kZfftCols columns per block; columns 2t and
-// 2t+1 share one complex transform.  Sums the KP partial grids on load.
-template <typename T>
+// Forward real FFT along z of CB columns per block; columns 2t and 2t+1
+// share one complex transform.  Sums the KP partial grids on load.
+template <typename T, int CB = kZfftCols>
 __device__ __forceinline__ void zfft_body(
     const T* __restrict__ H, int KP, long long pstride, T in_scale,
     cplx<T>* __restrict__ Fz, const Geo& g, const FftDesc& d,
@@ -899,7 +899,6 @@ __device__ __forceinline__ void zfft_body(
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
     const int M3 = g.M3;
     const int stride = M3 + 1;
-    constexpr int CB = kZfftCols;
     cplx<T>* B = A + (CB / 2) * stride;
     const long long ncol = g.ncol;
     const long long c0 = (long long)cbk * CB;
@@ -955,16 +954,16 @@ __device__ __forceinline__ void zfft_body(
     }
 }
 
-template <typename T>
+template <typename T, int CB>
 __global__ __launch_bounds__(256) void zfft_kernel(
     const T* __restrict__ H, int KP, long long pstride, T in_scale,
     cplx<T>* __restrict__ Fz, Geo g, FftDesc d,
     const cplx<T>* __restrict__ tw) {
-    zfft_body<T>(H, KP, pstride, in_scale, Fz, g, d, tw, blockIdx.x);
+    zfft_body<T, CB>(H, KP, pstride, in_scale, Fz, g, d, tw, blockIdx.x);
 }
 
 // Inverse real FFT along z; writes Ht[z][col] * out_scale.
-template <typename T>
+template <typename T, int CB = kZfftCols>
 __device__ __forceinline__ void zifft_body(
     const cplx<T>* __restrict__ Fz, T out_scale, T* __restrict__ Ht,
     const Geo& g, const FftDesc& d, const cplx<T>* __restrict__ tw, int cbk) {
@@ -972,7 +971,6 @@ __device__ __forceinline__ void zifft_body(
     cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
     const int M3 = g.M3;
     const int stride = M3 + 1;
-    constexpr int CB = kZfftCols;
     cplx<T>* B = A + (CB / 2) * stride;
     const long long ncol = g.ncol;
     const long long c0 = (long long)cbk * CB;
@@ -1011,11 +1009,11 @@ __device__ __forceinline__ void zifft_body(
     }
 }
 
-template <typename T>
+template <typename T, int CB>
 __global__ __launch_bounds__(256) void zifft_kernel(
     const cplx<T>* __restrict__ Fz, T out_scale, T* __restrict__ Ht, Geo g,
     FftDesc d, const cplx<T>* __restrict__ tw) {
-    zifft_body<T>(Fz, out_scale, Ht, g, d, tw, blockIdx.x);
+    zifft_body<T, CB>(Fz, out_scale, Ht, g, d, tw, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------
@@ -2512,6 +2510,40 @@ int launch_reduce_partials(const T* Hpart, int KP, long long pstride,
     return 0;
 }
 
+// Columns per block of one system's z transforms: 16 on grids of fewer
+// than 32768 columns (blocks of 32 would leave most CUs with one block:
+// 0.065 against 0.070 ms for the transform stage at FP64 N = 1e5, 9216
+// columns), 32 on larger ones (0.247 against 0.258 ms at FP32 N = 1e6).
+inline int zfft_cols(long long ncol) { return ncol < 32768 ? 16 : 32; }
+
+template <typename T>
+void launch_zfft(const T* Hin, int KP, long long pstride, T in_scale, cplx<T>* Fz,
+                 const Geo& g, const FftDesc& dz, const cplx<T>* tw, hipStream_t s) {
+    const int CB = zfft_cols(g.ncol);
+    const unsigned ncb = (unsigned)((g.ncol + CB - 1) / CB);
+    const size_t zsm = 2 * (CB / 2) * (size_t)(g.M3 + 1) * sizeof(cplx<T>);
+    if (CB == 16)
+        hipLaunchKernelGGL((zfft_kernel<T, 16>), dim3(ncb), dim3(256), zsm, s, Hin, KP,
+                           pstride, in_scale, Fz, g, dz, tw);
+    else
+        hipLaunchKernelGGL((zfft_kernel<T, 32>), dim3(ncb), dim3(256), zsm, s, Hin, KP,
+                           pstride, in_scale, Fz, g, dz, tw);
+}
+
+template <typename T>
+void launch_zifft(const cplx<T>* Fz, T out_scale, T* Ht, const Geo& g,
+                  const FftDesc& dz, const cplx<T>* tw, hipStream_t s) {
+    const int CB = zfft_cols(g.ncol);
+    const unsigned ncb = (unsigned)((g.ncol + CB - 1) / CB);
+    const size_t zsm = 2 * (CB / 2) * (size_t)(g.M3 + 1) * sizeof(cplx<T>);
+    if (CB == 16)
+        hipLaunchKernelGGL((zifft_kernel<T, 16>), dim3(ncb), dim3(256), zsm, s, Fz,
+                           out_scale, Ht, g, dz, tw);
+    else
+        hipLaunchKernelGGL((zifft_kernel<T, 32>), dim3(ncb), dim3(256), zsm, s, Fz,
+                           out_scale, Ht, g, dz, tw);
+}
+
 template <typename T>
 int launch_kspace(const T* Hin, int KP, long long pstride, T in_scale,
                   const Geo& g, int nslab, const SlabDesc* d_slabs,
@@ -2519,10 +2551,7 @@ int launch_kspace(const T* Hin, int KP, long long pstride, T in_scale,
                   const cplx<T>* tw, const T* S0, cplx<T>* Fz, cplx<T>* G,
                   T out_scale, T* Ht, hipStream_t s) {
     const size_t cs = sizeof(cplx<T>);
-    const unsigned ncb = (unsigned)((g.ncol + kZfftCols - 1) / kZfftCols);
-    const size_t zsm = 2 * (kZfftCols / 2) * (size_t)(g.M3 + 1) * cs;
-    hipLaunchKernelGGL(zfft_kernel<T>, dim3(ncb), dim3(256), zsm, s, Hin, KP,
-                       pstride, in_scale, Fz, g, dz, tw);
+    launch_zfft<T>(Hin, KP, pstride, in_scale, Fz, g, dz, tw, s);
     SE1P_CHECK_LAUNCH();
     int n1max = 0, n2max = 0;
     for (int i = 0; i < nslab; ++i) {
@@ -2543,8 +2572,7 @@ int launch_kspace(const T* Hin, int KP, long long pstride, T in_scale,
     hipLaunchKernelGGL(rowinv_kernel<T>, rgrid, dim3(256), rsm, s, G, Fz,
                        d_slabs, g, tw);
     SE1P_CHECK_LAUNCH();
-    hipLaunchKernelGGL(zifft_kernel<T>, dim3(ncb), dim3(256), zsm, s, Fz,
-                       out_scale, Ht, g, dz, tw);
+    launch_zifft<T>(Fz, out_scale, Ht, g, dz, tw, s);
     SE1P_CHECK_LAUNCH();
     return 0;
 }
@@ -2561,10 +2589,7 @@ int launch_kspace_ik(const T* Hin, int KP, long long pstride, const Geo& g,
                      cplx<T>* Fz, cplx<T>* G, cplx<T>* Gk, long long slab_elems,
                      T* Ht, T* Htk, long long gstride, hipStream_t s) {
     const size_t cs = sizeof(cplx<T>);
-    const unsigned ncb = (unsigned)((g.ncol + kZfftCols - 1) / kZfftCols);
-    const size_t zsm = 2 * (kZfftCols / 2) * (size_t)(g.M3 + 1) * cs;
-    hipLaunchKernelGGL(zfft_kernel<T>, dim3(ncb), dim3(256), zsm, s, Hin, KP,
-                       pstride, (T)1, Fz, g, dz, tw);
+    launch_zfft<T>(Hin, KP, pstride, (T)1, Fz, g, dz, tw, s);
     SE1P_CHECK_LAUNCH();
     int n1max = 0, n2max = 0;
     for (int i = 0; i < nslab; ++i) {
@@ -2592,8 +2617,7 @@ int launch_kspace_ik(const T* Hin, int KP, long long pstride, const Geo& g,
         hipLaunchKernelGGL(rowinv_kernel<T>, rgrid, dim3(256), rsm, s, Gd, Fz,
                            d_slabs, g, tw);
         SE1P_CHECK_LAUNCH();
-        hipLaunchKernelGGL(zifft_kernel<T>, dim3(ncb), dim3(256), zsm, s, Fz,
-                           (T)1, Hd, g, dz, tw);
+        launch_zifft<T>(Fz, (T)1, Hd, g, dz, tw, s);
         SE1P_CHECK_LAUNCH();
     }
     return 0;
