@@ -1615,9 +1615,10 @@ __global__ __launch_bounds__(64) void gather_kernel(
 // the staged position).  Candidates are staged in LDS in batches of 64, the
 // next batch's loads in flight while the current one is processed.  A first
 // pass sets, per lane, one bit per candidate of its quarter within the
-// cut-off; a second pass lets every lane pop its own bits, so the erfc and
-// exp run for in-range pairs only, with most lanes busy (bits left over
-// carry to the next batch's pass).  The four partial sums of a target are
+// cut-off (the target's own entry included: the second pass drops it); a
+// second pass lets every lane pop its own bits, so the erfc and exp run for
+// in-range pairs only, with most lanes busy (bits left over carry to the
+// next batch's pass).  The four partial sums of a target are
 // added with lane shuffles.
 // erfc(xi r) / r and the radial field factor q (erfc(xi r)/r +
 // 2 xi/sqrt(pi) exp(-xi^2 r^2)) / r^2 of one pair.  FP64 shares the
