@@ -282,6 +282,13 @@ def test_input_errors():
     with pytest.raises(se1p.SE1PError) as e:
         plan.eval(big, torch.zeros(17, device=dev, dtype=torch.float64))
     assert e.value.code == se1p.ERR_TOO_MANY
+    # an empty input is an argument error (N counts from 1), rejected on the
+    # host before anything is launched
+    qq = torch.tensor([1.0, -1.0], device=dev, dtype=torch.float64)
+    phi = torch.empty(2, device=dev, dtype=torch.float64)
+    assert se1p._lib().se1p_eval(plan._h, 0, se1p._ptr(x), se1p._ptr(qq), se1p._ptr(phi),
+                                 None, None, int(se1p.ALL)) == se1p.ERR_ARG
+    torch.cuda.synchronize()
 
 
 def test_check_input_accepts_fp32_rounded_neutral_charges():
