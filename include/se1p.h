@@ -186,6 +186,11 @@ int se1p_suggest_params(double tol, const double box[3], long long N,
  * tables, and allocates the device workspace for up to n_max particles on
  * the current HIP device.  stream: hipStream_t (NULL = default stream).
  * On success *out owns everything; free it with se1p_plan_destroy.
+ * The transforms take sizes with prime factors 2, 3 and 5 only: an M3 with
+ * another factor returns SE1P_ERR_UNSUPPORTED (the padded x and y sizes are
+ * rounded up to such sizes), as does an upsampled transform longer than
+ * 4096 or a grid whose transforms or gather planes would not fit one
+ * workgroup's LDS.
  */
 int se1p_plan_create(const se1p_params* params, long long n_max,
                      void* stream, se1p_plan** out);

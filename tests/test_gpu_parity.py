@@ -313,6 +313,17 @@ def test_input_errors():
     torch.cuda.synchronize()
 
 
+def test_plan_rejects_sizes_the_transforms_do_not_take():
+    # M3 = 14 = 2 x 7: the transforms take the radices 2, 3, 4 and 5 only;
+    # the plan reports it on creation and allocates nothing
+    _dev()
+    se1p = _se1p()
+    prm = se1p.make_params((1.0, 1.0, 1.0), 5.0, 14, 8, 2, 2.0, rc=0.3)
+    with pytest.raises(se1p.SE1PError) as e:
+        se1p.Plan(prm, n_max=10)
+    assert e.value.code == se1p.ERR_UNSUPPORTED
+
+
 def test_check_input_accepts_fp32_rounded_neutral_charges():
     """FP32 plans: charges neutral in FP64 and rounded to FP32 (|sum q| up to
     about sqrt(N) 3e-8) pass SE1P_CHECK_INPUT; a charge excess of 1e-3 sum |q|
